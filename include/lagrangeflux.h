@@ -1,0 +1,138 @@
+/*
+ * lagrangeflux.h -- C ABI of the MI355X (gfx950) Lagrange-flux library.
+ *
+ * The library advances the 2D compressible Euler equations of an ideal
+ * gas (Sec. 3 of De Vuyst, Gasc, Motte, Peybernes, Poncet, "Lagrange-flux
+ * schemes", arXiv:1607.08710) with the second-order Lagrange-flux scheme of
+ * Sec. 5: per face, MUSCL reconstruction of the primitive variables with
+ * the Sweby limiter (eq. (sweby)), the Lagrangian HLL acoustic solve for
+ * (u*, p*) (eqs. (13)-(14)), upwinding on the sign of u* and the flux of
+ * eq. (12); per cell, the conservative update of eq. (11) inside the Heun
+ * predictor-corrector of Sec. 5, with dt from a global CFL reduction.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - State arrays are DEVICE pointers owned by the caller, contiguous, in
+ *    structure-of-arrays layout U[f][j][i]: f = 0..3 for (rho, rho*u, rho*v,
+ *    rho*E), j = 0..ny-1 the y index, i = 0..nx-1 the x index (fastest).
+ *    Element type is double (LF_F64) or float (LF_F32), per the context.
+ *  - ws is a DEVICE workspace of at least the size lf_init reports, owned
+ *    by the caller, 256-byte aligned.  It holds the predictor state U*, the
+ *    adjoint intermediate, the reduction cells and the device-side dt / t /
+ *    step counters.  One workspace must not be used by two calls that run
+ *    concurrently.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; "async" calls return before it runs.
+ *  - The library never allocates device memory and never frees caller
+ *    memory.
+ *  - Every call returns an lf_status.  Argument errors are detected on the
+ *    host before anything is enqueued.  A context is not thread-safe;
+ *    distinct contexts are independent.
+ */
+#ifndef LAGRANGEFLUX_H
+#define LAGRANGEFLUX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lf_ctx lf_ctx; /* opaque, host memory only */
+
+typedef enum {
+    LF_OK = 0,
+    LF_ERR_ARG = 1,          /* invalid argument (null, size, range, aliasing) */
+    LF_ERR_HIP = 2,          /* a HIP runtime call failed                       */
+    LF_ERR_NONPHYSICAL = 3,  /* a state with rho <= 0, p <= 0 or a non-finite
+                                value was detected                             */
+    LF_ERR_STATE = 4         /* misuse of the context (e.g. dtype mismatch)     */
+} lf_status;
+
+typedef enum { LF_F64 = 0, LF_F32 = 1 } lf_dtype;
+typedef enum { LF_BC_PERIODIC = 0, LF_BC_TRANSMISSIVE = 1 } lf_bc;
+
+typedef struct {
+    int32_t nx, ny;   /* cells along x and y; 1 <= nx, ny; nx*ny < 2^31        */
+    double dx, dy;    /* uniform cell sizes, > 0                                */
+    double gamma;     /* ratio of specific heats, in (1, 3] (Sec. 3)            */
+    double cfl;       /* CFL number, > 0 (Heun list, item 1)                    */
+    double beta;      /* Sweby coefficient, in [0, 2]; the paper's range for
+                         second order is [1, 2] (eq. (sweby)); 0 gives the
+                         first-order scheme                                     */
+    int32_t bc_x;     /* lf_bc along x: periodic wraps the index, transmissive
+                         clamps it (ghost cells copy the edge cell)             */
+    int32_t bc_y;     /* lf_bc along y                                          */
+    int32_t dtype;    /* lf_dtype of every state / adjoint array                */
+} lf_params;
+
+/* Validates *params, creates a context and reports the workspace size in
+ * bytes.  Makes no HIP call.  LF_ERR_ARG on a null pointer or an
+ * out-of-range parameter.  The context is released by lf_destroy. */
+int lf_init(const lf_params *params, lf_ctx **out, size_t *workspace_bytes);
+
+/* Releases a context (NULL is accepted). */
+void lf_destroy(lf_ctx *ctx);
+
+/* Static English text for an lf_status value. */
+const char *lf_status_string(int status);
+
+/* CFL time step of state U (Heun list, item 1):
+ *   dt = cfl / max_K [ (|u|+c)/dx + (|v|+c)/dy ],  c = sqrt(gamma p / rho),
+ * reduced in FP64.  Synchronises the stream and writes *dt_out.  Returns
+ * LF_ERR_NONPHYSICAL (and *dt_out = 0) if any cell has rho <= 0, p <= 0
+ * or a non-finite value. */
+int lf_dt(lf_ctx *ctx, const void *U, void *ws, void *stream, double *dt_out);
+
+/* One Heun step at the caller's dt (Sec. 5, items 2-11), async:
+ *   U*      = U^n - dt R(U^n)
+ *   U^{n+1} = (U^n + U* - dt R(U*)) / 2,
+ * algebraically the paper's U^n - dt (R(U^n) + R(U*)) / 2.  R(U) is the
+ * flux balance of eq. (11).  Unp1 may equal Un (in-place update); any other
+ * overlap is LF_ERR_ARG.  dt must be finite and >= 0.  In the FP32 context
+ * the states are float, the flux arithmetic is float and every stage
+ * update is formed in FP64 and rounded once. */
+int lf_step(lf_ctx *ctx, const void *Un, void *Unp1, double dt, void *ws, void *stream);
+
+/* Advances U in place from t0 until t_end or max_steps steps, each step
+ * with dt = min(CFL dt of the current state, t_end - t); the step that is
+ * clamped lands exactly on t_end.  dt and t stay on the device; the host
+ * synchronises once per batch of steps.  Writes the final time, the step
+ * count, and (if dts_out != NULL) the dt of the first min(steps,
+ * dts_capacity) steps into the host array dts_out.  Returns
+ * LF_ERR_NONPHYSICAL if the initial state or any state produced is
+ * non-physical (the state of that step is left in U). */
+int lf_advance(lf_ctx *ctx, void *U, double t0, double t_end, int64_t max_steps,
+               void *ws, void *stream, double *t_out, int64_t *steps_out,
+               double *dts_out, int64_t dts_capacity);
+
+/* Residual R(U) of eq. (11), (F_{i+1/2} - F_{i-1/2})/dx + (G_{j+1/2} -
+ * G_{j-1/2})/dy, written to R (same layout and dtype as U), async.  R must
+ * not overlap U. */
+int lf_residual(lf_ctx *ctx, const void *U, void *R, void *ws, void *stream);
+
+/* Vector-Jacobian product out = J_R(U)^T g of the residual, async.  The
+ * derivative conventions at the non-differentiable points are: limiter
+ * derivative zero when ab <= 0, min follows its first argument on ties,
+ * max(m1, m2) follows m1 on ties, max(c_L, c_R) follows c_L on ties, the
+ * upwind side is left iff u* > 0.  out must not overlap U or g. */
+int lf_residual_vjp(lf_ctx *ctx, const void *U, const void *g, void *out, void *ws,
+                    void *stream);
+
+/* Adjoint of one lf_step at the frozen dt, async: given lam_np1 =
+ * dJ/dU^{n+1}, writes lam_n = dJ/dU^n, recomputing U* from Un:
+ *   mu    = (lam_np1 - dt J_R(U*)^T lam_np1) / 2
+ *   lam_n = lam_np1 / 2 + mu - dt J_R(U^n)^T mu.
+ * lam_n must not overlap Un or lam_np1. */
+int lf_adjoint_step(lf_ctx *ctx, const void *Un, double dt, const void *lam_np1,
+                    void *lam_n, void *ws, void *stream);
+
+/* Conservation totals: out[f] = dx*dy * sum_K U_f(K), summed in FP64 with
+ * compensation in a fixed order (deterministic).  Synchronises. */
+int lf_totals(lf_ctx *ctx, const void *U, void *ws, void *stream, double out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAGRANGEFLUX_H */

@@ -1,0 +1,249 @@
+"""Plain FP64 CPU oracle of the second-order Lagrange-flux scheme.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The
+product path (``paper_1607_08710_amd``) never imports it, and the two share
+no code: the oracle is the C file ``lfo.c`` next to this module, loaded
+here through ctypes.
+
+Arrays are numpy float64, C-contiguous, shape (4, ny, nx) with the fields
+(rho, rho*u, rho*v, rho*E) and x fastest.
+
+Functions follow the paper (De Vuyst et al., arXiv:1607.08710): the
+Euler system and perfect-gas EOS of Sec. 3, the semi-discrete flux form of
+eqs. (11)-(12), the Sweby limiter of eq. (sweby), the Lagrangian HLL solver
+of eqs. (13)-(14) and the Heun predictor-corrector list of Sec. 5.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liblfo.so")
+
+PERIODIC = 0
+TRANSMISSIVE = 1
+
+OK = 0
+ERR_ARG = 1
+ERR_NONPHYSICAL = 3
+ERR_VACUUM = 5
+
+
+def build(force: bool = True) -> str:
+    """Compile lfo.c into liblfo.so (gcc, no contraction, no fast-math)."""
+    if force or not os.path.exists(_SO):
+        cmd = [
+            "gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+            "-fPIC", "-shared", "-Wall", "-Wextra", "-o", _SO,
+            os.path.join(_HERE, "lfo.c"), "-lm",
+        ]
+        subprocess.run(cmd, check=True)
+    return _SO
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("beta", ctypes.c_double),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+    ]
+
+
+@dataclass(frozen=True)
+class Params:
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    gamma: float = 1.4
+    cfl: float = 0.5
+    beta: float = 1.5
+    bc_x: int = PERIODIC
+    bc_y: int = PERIODIC
+
+    def c(self) -> _Params:
+        return _Params(self.nx, self.ny, self.dx, self.dy, self.gamma, self.cfl,
+                       self.beta, self.bc_x, self.bc_y)
+
+    def with_(self, **kw) -> "Params":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Params(**d)
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_P = ctypes.POINTER(_Params)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        L.lfo_cons_to_prim.argtypes = [d, _D, _D]
+        L.lfo_cons_to_prim.restype = None
+        L.lfo_sweby.argtypes = [d, d, d]
+        L.lfo_sweby.restype = d
+        L.lfo_acoustic_solve.argtypes = [d, d, d, d, d, d, d, _D, _D]
+        L.lfo_acoustic_solve.restype = None
+        L.lfo_face_flux.argtypes = [d, _D, _D, _D]
+        L.lfo_face_flux.restype = None
+        L.lfo_residual.argtypes = [_P, _D, _D]
+        L.lfo_dt.argtypes = [_P, _D, _D]
+        L.lfo_step.argtypes = [_P, _D, d, _D]
+        L.lfo_advance.argtypes = [_P, _D, d, d, i64, _D, ctypes.POINTER(i64), _D]
+        L.lfo_totals.argtypes = [_P, _D, _D]
+        L.lfo_totals.restype = None
+        L.lfo_residual_jvp.argtypes = [_P, _D, _D, _D]
+        L.lfo_residual_vjp.argtypes = [_P, _D, _D, _D]
+        L.lfo_tlm_step.argtypes = [_P, _D, d, _D, _D]
+        L.lfo_adjoint_step.argtypes = [_P, _D, d, _D, _D]
+        L.lfo_exact_riemann.argtypes = [d, d, d, d, d, d, d, i64, _D, _D, _D, _D, _D, _D]
+        for name in ("lfo_residual", "lfo_dt", "lfo_step", "lfo_advance", "lfo_residual_jvp",
+                     "lfo_residual_vjp", "lfo_tlm_step", "lfo_adjoint_step", "lfo_exact_riemann"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _state(P: Params, U) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if U.shape != (4, P.ny, P.nx):
+        raise ValueError(f"state shape {U.shape} != (4, {P.ny}, {P.nx})")
+    return U
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise RuntimeError(f"{what} returned {rc}")
+
+
+# ---- pointwise pieces ----------------------------------------------------
+
+def cons_to_prim(gamma: float, U4) -> np.ndarray:
+    U4 = np.ascontiguousarray(U4, dtype=np.float64)
+    w = np.empty(4)
+    lib().lfo_cons_to_prim(gamma, _ptr(U4), _ptr(w))
+    return w
+
+
+def sweby(a: float, b: float, beta: float) -> float:
+    return lib().lfo_sweby(a, b, beta)
+
+
+def acoustic_solve(gamma, rho_l, u_l, p_l, rho_r, u_r, p_r):
+    us, ps = ctypes.c_double(), ctypes.c_double()
+    lib().lfo_acoustic_solve(gamma, rho_l, u_l, p_l, rho_r, u_r, p_r,
+                             ctypes.byref(us), ctypes.byref(ps))
+    return us.value, ps.value
+
+
+def face_flux(gamma: float, wl, wr) -> np.ndarray:
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    phi = np.empty(4)
+    lib().lfo_face_flux(gamma, _ptr(wl), _ptr(wr), _ptr(phi))
+    return phi
+
+
+# ---- grid operators --------------------------------------------------------
+
+def residual(P: Params, U) -> np.ndarray:
+    U = _state(P, U)
+    R = np.empty_like(U)
+    _check(lib().lfo_residual(ctypes.byref(P.c()), _ptr(U), _ptr(R)), "lfo_residual")
+    return R
+
+
+def dt(P: Params, U):
+    """Returns (rc, dt); rc == ERR_NONPHYSICAL flags a non-physical state."""
+    U = _state(P, U)
+    out = ctypes.c_double()
+    rc = lib().lfo_dt(ctypes.byref(P.c()), _ptr(U), ctypes.byref(out))
+    return rc, out.value
+
+
+def step(P: Params, U, dt_: float) -> np.ndarray:
+    U = _state(P, U)
+    out = np.empty_like(U)
+    _check(lib().lfo_step(ctypes.byref(P.c()), _ptr(U), dt_, _ptr(out)), "lfo_step")
+    return out
+
+
+def advance(P: Params, U, t0: float, t_end: float, max_steps: int = 10**9,
+            record_dts: bool = True):
+    """Returns (U_final, t, steps, dts, rc)."""
+    U = np.array(_state(P, U), copy=True)
+    t = ctypes.c_double()
+    steps = ctypes.c_int64()
+    cap = int(min(max_steps, 10**7)) if record_dts else 0
+    dts = np.empty(max(cap, 1))
+    rc = lib().lfo_advance(ctypes.byref(P.c()), _ptr(U), t0, t_end, max_steps,
+                           ctypes.byref(t), ctypes.byref(steps),
+                           _ptr(dts) if record_dts else None)
+    return U, t.value, steps.value, dts[: steps.value].copy() if record_dts else None, rc
+
+
+def totals(P: Params, U) -> np.ndarray:
+    U = _state(P, U)
+    out = np.empty(4)
+    lib().lfo_totals(ctypes.byref(P.c()), _ptr(U), _ptr(out))
+    return out
+
+
+def residual_jvp(P: Params, U, dU) -> np.ndarray:
+    U, dU = _state(P, U), _state(P, dU)
+    out = np.empty_like(U)
+    _check(lib().lfo_residual_jvp(ctypes.byref(P.c()), _ptr(U), _ptr(dU), _ptr(out)), "jvp")
+    return out
+
+
+def residual_vjp(P: Params, U, g) -> np.ndarray:
+    U, g = _state(P, U), _state(P, g)
+    out = np.empty_like(U)
+    _check(lib().lfo_residual_vjp(ctypes.byref(P.c()), _ptr(U), _ptr(g), _ptr(out)), "vjp")
+    return out
+
+
+def tlm_step(P: Params, U, dt_: float, dU) -> np.ndarray:
+    U, dU = _state(P, U), _state(P, dU)
+    out = np.empty_like(U)
+    _check(lib().lfo_tlm_step(ctypes.byref(P.c()), _ptr(U), dt_, _ptr(dU), _ptr(out)), "tlm")
+    return out
+
+
+def adjoint_step(P: Params, U, dt_: float, lam) -> np.ndarray:
+    U, lam = _state(P, U), _state(P, lam)
+    out = np.empty_like(U)
+    _check(lib().lfo_adjoint_step(ctypes.byref(P.c()), _ptr(U), dt_, _ptr(lam), _ptr(out)),
+           "adjoint")
+    return out
+
+
+def exact_riemann(gamma: float, left, right, xi):
+    """Exact ideal-gas Riemann solution at xi = (x - x0)/t.
+
+    left/right = (rho, u, p).  Returns (rho, u, p, p_star, u_star)."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = xi.size
+    rho, u, p = np.empty(n), np.empty(n), np.empty(n)
+    ps, us = ctypes.c_double(), ctypes.c_double()
+    rc = lib().lfo_exact_riemann(gamma, *map(float, left), *map(float, right), n, _ptr(xi),
+                                 _ptr(rho), _ptr(u), _ptr(p), ctypes.byref(ps), ctypes.byref(us))
+    _check(rc, "lfo_exact_riemann")
+    return rho, u, p, ps.value, us.value
