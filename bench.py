@@ -1,0 +1,327 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the gfx950 Lagrange-flux library on one GPU.
+
+Workload: the periodic Kelvin-Helmholtz shear layer at 16384^2 cells (rho 2
+with u = 0.5 inside |y - 1/2| < 1/4, rho 1 with u = -0.5 outside, p = 2.5,
+v = 0.01 sin(4 pi x)), synthetic inputs built on the device.  A step is one
+full Heun step of the scheme: predictor stage, corrector stage with the
+fused CFL reduction, and the device-side dt update, all through lf_advance.
+
+Prints ONE JSON line on stdout: the FP64 cell-updates/s as ``value``, the
+FP32 path and the adjoint (lf_adjoint_step and the checkpointed full
+gradient at 4096^2) as extra objects, the HBM roofline of the dominant
+kernel (the FP64 corrector stage) measured with HIP events on the stream it
+runs on, and the FP64 CPU oracle timed on a bounded sample on this host.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+  python bench.py --profile-pass kernels   # short fixed sequence for rocprofv3
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
+BYTES_PER_CELL = {               # algorithmic (compulsory) bytes per cell
+    ("corrector", 8): 96, ("predictor", 8): 64, ("step", 8): 160,
+    ("corrector", 4): 48, ("predictor", 4): 32, ("step", 4): 80,
+    ("adjoint_step", 8): 288, ("adjoint_step", 4): 144,
+}
+KERNEL_SOURCES = ["paper_1607_08710_amd/csrc/lf_forward.hip", "paper_1607_08710_amd/csrc/lf_device.h",
+                  "paper_1607_08710_amd/csrc/lf_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kh16384.json")
+METRIC = "cell-updates/s per step (FP64 vs FP32, % HBM roofline) + adjoint step/s at 4096^2"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_solver(L, cfg, dtype):
+    return L.Solver(L.Params(cfg["nx"], cfg["ny"], cfg["dx"], cfg["dy"], cfg["gamma"], cfg["cfl"],
+                             cfg["beta"], cfg["bc_x"], cfg["bc_y"], dtype))
+
+
+def time_advance(S, U, steps, warmup):
+    """Warm up, then time `steps` full steps of lf_advance between events."""
+    import torch
+    if warmup:
+        S.advance(U, 0.0, math.inf, max_steps=warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    t, n, _ = S.advance(U, 0.0, math.inf, max_steps=steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert n == steps, (n, steps)
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def time_stages(S, U, reps):
+    """Average duration of the predictor and corrector kernels, each launch
+    bracketed by HIP events on the stream the library launches on."""
+    import torch
+    dt = S.dt(U)
+    Us = S.empty_state()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2 * reps)]
+    for k in range(reps):
+        a, b = ev[2 * k]
+        a.record()
+        S.stage(1, U, Us, dt)
+        b.record()
+        a, b = ev[2 * k + 1]
+        a.record()
+        S.stage(2, Us, U, dt, base=U, reduce=True)  # in place, as in lf_advance
+        b.record()
+    torch.cuda.synchronize()
+    pred = sum(ev[2 * k][0].elapsed_time(ev[2 * k][1]) for k in range(reps)) / reps
+    corr = sum(ev[2 * k + 1][0].elapsed_time(ev[2 * k + 1][1]) for k in range(reps)) / reps
+    del Us
+    return pred / 1e3, corr / 1e3
+
+
+def forward_leg(L, W, n, dtype_flag, steps, warmup, reps):
+    import torch
+    tdt = torch.float64 if dtype_flag == L.LF_F64 else torch.float32
+    esz = 8 if dtype_flag == L.LF_F64 else 4
+    U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt)
+    S = make_solver(L, cfg, dtype_flag)
+    tot0 = S.totals(U)
+    sec, wall = time_advance(S, U, steps, warmup)
+    tot1 = S.totals(U)
+    cells = n * n
+    cups = cells * steps / sec
+    pred, corr = time_stages(S, U, reps)
+    drift = [float(b - a) for a, b in zip(tot0, tot1)]
+    res = {
+        "value": cups, "ms_per_step": 1e3 * sec / steps, "wall_s": wall,
+        "step_effective_GBps": BYTES_PER_CELL[("step", esz)] * cells * steps / sec / 1e9,
+        "predictor_ms": 1e3 * pred, "corrector_ms": 1e3 * corr,
+        "predictor_GBps": BYTES_PER_CELL[("predictor", esz)] * cells / pred / 1e9,
+        "corrector_GBps": BYTES_PER_CELL[("corrector", esz)] * cells / corr / 1e9,
+        "totals_initial": [float(a) for a in tot0], "totals_drift": drift,
+    }
+    del U, S
+    torch.cuda.empty_cache()
+    return res
+
+
+def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
+    """Bare lf_adjoint_step rate, and the full gradient (forward + recompute
+    + adjoint) of a steps-long rollout with checkpoints every ckpt steps."""
+    import torch
+    from paper_1607_08710_amd import rollout
+    tdt = torch.float64 if dtype_flag == L.LF_F64 else torch.float32
+    U0, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt)
+    S = make_solver(L, cfg, dtype_flag)
+    dt = S.dt(U0)
+    lam = torch.randn_like(U0)
+    out = torch.empty_like(U0)
+    S.adjoint_step(U0, dt, lam, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        S.adjoint_step(U0, dt, lam, out)
+    e1.record()
+    torch.cuda.synchronize()
+    bare = e0.elapsed_time(e1) / 1e3 / reps
+    # full gradient of J = 1/2 dx dy sum (rho_N - rho_0)^2 w.r.t. U0
+    rho_t = U0[0].clone()
+    x = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    e0.record()
+    UN = rollout(x, S, [dt] * steps, ckpt_every=ckpt)
+    J = 0.5 * cfg["dx"] * cfg["dy"] * ((UN[0] - rho_t) ** 2).sum()
+    J.backward()
+    e1.record()
+    torch.cuda.synchronize()
+    full = e0.elapsed_time(e1) / 1e3
+    esz = 8 if dtype_flag == L.LF_F64 else 4
+    res = {
+        "lf_adjoint_step_per_s": 1.0 / bare,
+        "lf_adjoint_step_ms": 1e3 * bare,
+        "lf_adjoint_step_GBps": BYTES_PER_CELL[("adjoint_step", esz)] * n * n / bare / 1e9,
+        "full_gradient_steps_per_s": steps / full,
+        "full_gradient_s": full,
+        "grad_finite": bool(torch.isfinite(x.grad).all().item()),
+    }
+    del U0, S, lam, out, x, UN
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(W, n=2048, min_seconds=10.0, max_steps=400):
+    """FP64 oracle on the same Kelvin-Helmholtz recipe at n^2, as many steps
+    as fit in ~min_seconds (at least 2), on this host's cores."""
+    import oracle
+    U, cfg = W.kelvin_helmholtz(n)
+    P = oracle.Params(cfg["nx"], cfg["ny"], cfg["dx"], cfg["dy"], cfg["gamma"], cfg["cfl"], cfg["beta"],
+                      cfg["bc_x"], cfg["bc_y"])
+    rc, dt = oracle.dt(P, U)
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < 2 or (time.perf_counter() - t0 < min_seconds and steps < max_steps):
+        U = oracle.step(P, U, dt)
+        steps += 1
+    sec = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return {"value": n * n * steps / sec, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"Kelvin-Helmholtz {n}^2, {steps} FP64 Heun steps at fixed dt ({sec:.1f} s), "
+                      f"OMP_NUM_THREADS={cores}"}
+
+
+def traffic_entry(n):
+    """HBM bytes per corrector launch from the committed rocprofv3 counter
+    summary, or None when absent or taken from other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    if rec.get("n") != n:
+        return None, "counters taken at another size"
+    return rec.get("corrector_f64_bytes"), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel"
+
+
+def profile_pass(L, W, n):
+    """Fixed short sequence for rocprofv3: each stage kernel of both
+    precisions a few times, then a plain device copy of known size."""
+    import torch
+    for flag, tdt in ((L.LF_F64, torch.float64), (L.LF_F32, torch.float32)):
+        U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt)
+        S = make_solver(L, cfg, flag)
+        S.advance(U, 0.0, math.inf, max_steps=3)
+        time_stages(S, U, 5)
+        torch.cuda.synchronize()
+        del U, S
+        torch.cuda.empty_cache()
+    # plain copy kernel: 1 GiB read + 1 GiB written per launch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile pass done")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=16384, help="grid cells per side")
+    ap.add_argument("--adj-n", type=int, default=4096)
+    ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--adj-ckpt", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="forward,adjoint,cpu",
+                    help="comma list of legs to run: forward, adjoint, cpu (profiling runs use one leg "
+                         "so that each kernel runs at one grid size)")
+    ap.add_argument("--profile-pass", choices=["none", "kernels"], default="none")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the Lagrange-flux path is built and measured on a single "
+              "MI355X (multi-GPU domain decomposition is a design, not part of this build); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1607_08710_amd as L
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    L.lib()
+
+    if args.profile_pass == "kernels":
+        profile_pass(L, W, args.n)
+        return
+
+    legs = set(x.strip() for x in args.legs.split(",") if x.strip())
+    f64 = f32 = adj64 = adj32 = roofline = cpu = None
+    if "forward" in legs:
+        log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
+        f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
+        log(f"FP64 {f64['value'] / 1e9:.2f} G cell-updates/s, {f64['ms_per_step']:.3f} ms/step")
+        log(f"FP32 Kelvin-Helmholtz {args.n}^2")
+        f32 = forward_leg(L, W, args.n, L.LF_F32, args.steps, args.warmup, args.kernel_reps)
+        f32["ratio_vs_fp64"] = f32["value"] / f64["value"]
+        log(f"FP32 {f32['value'] / 1e9:.2f} G cell-updates/s, {f32['ms_per_step']:.3f} ms/step")
+        cells = args.n * args.n
+        corr_s = f64["corrector_ms"] / 1e3
+        achieved = BYTES_PER_CELL[("corrector", 8)] * cells / corr_s / 1e9
+        traffic, traffic_src = traffic_entry(args.n)
+        roofline = {"bound": "hbm", "kernel": "lf::stage_kernel<double, 2, 0, 0> (FP64 corrector, periodic)",
+                    "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "traffic_source": traffic_src,
+                    "algorithmic_bytes_per_cell": BYTES_PER_CELL[("corrector", 8)], "cells_per_launch": cells,
+                    "avg_launch_ms": f64["corrector_ms"]}
+    if "adjoint" in legs:
+        log(f"adjoint {args.adj_n}^2, {args.adj_steps} steps, checkpoints every {args.adj_ckpt}")
+        adj64 = adjoint_leg(L, W, args.adj_n, L.LF_F64, args.adj_steps, args.adj_ckpt, 10)
+        log(f"adjoint FP64: {adj64['lf_adjoint_step_per_s']:.1f} lf_adjoint_step/s, "
+            f"{adj64['full_gradient_steps_per_s']:.1f} full-gradient steps/s")
+        adj32 = adjoint_leg(L, W, args.adj_n, L.LF_F32, args.adj_steps, args.adj_ckpt, 10)
+        log(f"adjoint FP32: {adj32['lf_adjoint_step_per_s']:.1f} lf_adjoint_step/s")
+    if "cpu" in legs and not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        cpu = cpu_baseline(W, min_seconds=args.cpu_seconds)
+        log(f"oracle {cpu['value'] / 1e6:.2f} M cell-updates/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": f64["value"] if f64 else None,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"] if f64 else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Kelvin-Helmholtz shear layer, periodic, {args.n}^2 cells, gamma 1.4, "
+                               f"CFL 0.5, Sweby beta 1.5, Heun steps via lf_advance",
+                   "nx": args.n, "ny": args.n, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": f64,
+        "fp32": f32,
+        "adjoint": {"n": args.adj_n, "steps": args.adj_steps, "ckpt_every": args.adj_ckpt,
+                    "f64": adj64, "f32": adj32},
+        "paper_context": {"value": 81.0e6, "unit": "cell-updates/s",
+                          "hardware": "2 x 8-core Intel Sandy Bridge E5-2670, AVX, OpenMP",
+                          "workload": "mesh unspecified (fine meshes in DRAM)"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

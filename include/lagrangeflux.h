@@ -95,6 +95,16 @@ int lf_dt(lf_ctx *ctx, const void *U, void *ws, void *stream, double *dt_out);
  * update is formed in FP64 and rounded once. */
 int lf_step(lf_ctx *ctx, const void *Un, void *Unp1, double dt, void *ws, void *stream);
 
+/* One stage of the Heun step at the caller's dt, async (the two kernels
+ * lf_step chains, exposed for callers that schedule stages themselves):
+ *   stage 1 (predictor, items 2-6):  out = in - dt R(in)
+ *   stage 2 (corrector, items 7-11): out = (base + in - dt R(in)) / 2
+ * base is read for stage 2 only and may equal out; in must not overlap out.
+ * With reduce != 0, stage 2 also reduces the CFL wave speed of out into
+ * the workspace (as lf_advance does); the result is not returned. */
+int lf_stage(lf_ctx *ctx, int stage, const void *in, const void *base, void *out, double dt,
+             int reduce, void *ws, void *stream);
+
 /* Advances U in place from t0 until t_end or max_steps steps, each step
  * with dt = min(CFL dt of the current state, t_end - t); the step that is
  * clamped lands exactly on t_end.  dt and t stay on the device; the host

@@ -1,0 +1,256 @@
+// lf_device.h -- device-side building blocks of the gfx950 Lagrange-flux
+// kernels (De Vuyst et al., arXiv:1607.08710).  Everything here is
+// templated on the arithmetic type T (double or float) and is inlined into
+// the stage and adjoint kernels.
+//
+// The x- and y-faces call the same face routine with the frame
+// (rho, u_n, u_t, p), so the two directions execute identical arithmetic.
+// No floating-point contraction is left to the compiler (built with
+// -ffp-contract=off); every fused multiply-add below is explicit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf {
+
+constexpr int kWave = 64;        // wavefront width on CDNA
+constexpr int kHalo = 2;         // stencil half-width along each axis
+constexpr int kTileW = kWave - 2 * kHalo;  // output columns per wave (60)
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
+constexpr int kDtHist = 4096;    // per-step dt records kept on the device
+
+enum : int { kBcPeriodic = 0, kBcTransmissive = 1 };
+
+// Device control block, stored at the start of the control area of the
+// workspace.  dt and t of the time loop live here so that the loop never
+// round-trips to the host between steps.
+struct Ctl {
+  unsigned long long smax;   // max wave speed of the last reduced state, as
+                             // the bit pattern of a non-negative double
+  unsigned int flag;         // non-zero once a non-physical state was seen
+  unsigned int done;         // non-zero once the time loop has finished
+  double dt;                 // time step of the step in flight
+  double t;                  // time at the start of the step in flight
+  double t_end;
+  long long step;            // completed steps
+  long long max_steps;
+  double cfl;
+  unsigned int clamped;      // the step in flight was clamped to t_end
+  unsigned int pad;
+  double totals[4];          // result of the conservation-totals reduction
+  double dt_hist[kDtHist];   // dt of step k stored at k % kDtHist
+};
+
+// ---- boundary index mapping ------------------------------------------------
+
+template <int BC>
+__device__ __forceinline__ int map_index(int k, int n) {
+  if constexpr (BC == kBcPeriodic) {
+    k %= n;
+    return k < 0 ? k + n : k;
+  } else {
+    return k < 0 ? 0 : (k >= n ? n - 1 : k);
+  }
+}
+
+// ---- cross-lane shifts (DPP whole-wave shifts, all 64 lanes active) -------
+
+// Lane l receives the value of lane l-1 (lane 0 receives 0).
+__device__ __forceinline__ int shr1_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+// Lane l receives the value of lane l+1 (lane 63 receives 0).
+__device__ __forceinline__ int shl1_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ double shr1(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(shr1_i(hi), shr1_i(lo));
+}
+__device__ __forceinline__ double shl1(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(shl1_i(hi), shl1_i(lo));
+}
+__device__ __forceinline__ float shr1(float v) {
+  return __int_as_float(shr1_i(__float_as_int(v)));
+}
+__device__ __forceinline__ float shl1(float v) {
+  return __int_as_float(shl1_i(__float_as_int(v)));
+}
+
+// ---- primitive variables (perfect gas, Sec. 3) -----------------------------
+
+template <typename T>
+struct Prim {
+  T r, u, v, p;
+};
+
+template <typename T>
+__device__ __forceinline__ Prim<T> to_prim(T q0, T q1, T q2, T q3, T gm1) {
+  Prim<T> w;
+  T ir = T(1) / q0;
+  w.r = q0;
+  w.u = q1 * ir;
+  w.v = q2 * ir;
+  // p = (gamma-1) (rho E - (m_x u + m_y v)/2)
+  T ke = T(0.5) * (q1 * w.u + q2 * w.v);
+  w.p = gm1 * (q3 - ke);
+  return w;
+}
+
+// ---- Sweby limiter, eq. (sweby) ---------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T sweby(T a, T b, T beta) {
+  T aa = fabs(a), ab = fabs(b);
+  T m = fmax(fmin(aa, beta * ab), fmin(beta * aa, ab));
+  return (a * b > T(0)) ? copysign(m, a) : T(0);
+}
+
+// Partial derivatives of sweby(a, b) with the conventions: zero when
+// ab <= 0; min(x, y) follows x when x <= y; max(m1, m2) follows m1 when
+// m1 >= m2.  (a and b share their sign when ab > 0, so the sign factors
+// cancel.)
+template <typename T>
+__device__ __forceinline__ void sweby_d(T a, T b, T beta, T& da, T& db) {
+  T aa = fabs(a), ab = fabs(b);
+  T bb = beta * ab, ba = beta * aa;
+  bool m1a = aa <= bb;               // m1 = |a| (else beta |b|)
+  bool m2a = ba <= ab;               // m2 = beta |a| (else |b|)
+  T m1 = m1a ? aa : bb;
+  T m2 = m2a ? ba : ab;
+  bool first = m1 >= m2;
+  T d1a = m1a ? T(1) : T(0), d1b = m1a ? T(0) : beta;
+  T d2a = m2a ? beta : T(0), d2b = m2a ? T(0) : T(1);
+  bool act = a * b > T(0);
+  da = act ? (first ? d1a : d2a) : T(0);
+  db = act ? (first ? d1b : d2b) : T(0);
+}
+
+// ---- face flux: Lagrangian HLL solve (eqs. (13)-(14)) + upwind + eq. (12) --
+
+// State on one side of a face, in the face frame.
+template <typename T>
+struct FaceState {
+  T r, un, ut, p;
+};
+
+template <typename T>
+struct Flux {
+  T f0, f1, f2, f3;  // mass, normal momentum, tangential momentum, energy
+};
+
+template <typename T>
+__device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceState<T>& R,
+                                             T gamma, T inv_gm1) {
+  // a = max(c_L, c_R) = sqrt(max(gamma p_L / rho_L, gamma p_R / rho_R))
+  T cl2 = gamma * L.p / L.r;
+  T cr2 = gamma * R.p / R.r;
+  T a = sqrt(fmax(cl2, cr2));
+  T S = L.r + R.r;
+  T iS = T(1) / S;
+  // eq. (13): p* = (rho_R p_L + rho_L p_R)/S - (rho_L rho_R / S) a (u_R - u_L)
+  T ps = (R.r * L.p + L.r * R.p) * iS - (L.r * R.r * iS) * a * (R.un - L.un);
+  // eq. (14): u* = (rho_L u_L + rho_R u_R)/S - (p_R - p_L)/(S a)
+  T us = (L.r * L.un + R.r * R.un) * iS - iS * (R.p - L.p) / a;
+  // upwind on the sign of u*: left when u* > 0
+  bool left = us > T(0);
+  T r = left ? L.r : R.r;
+  T un = left ? L.un : R.un;
+  T ut = left ? L.ut : R.ut;
+  T p = left ? L.p : R.p;
+  T E = p * inv_gm1 + T(0.5) * r * (un * un + ut * ut);
+  T m = r * us;
+  Flux<T> F;
+  F.f0 = m;
+  F.f1 = m * un + ps;
+  F.f2 = m * ut;
+  F.f3 = (E + ps) * us;
+  return F;
+}
+
+// Vector-Jacobian product of face_flux: given the flux cotangent Fb,
+// returns the cotangents of the two face states.  Conventions at the
+// kinks: max(c_L^2, c_R^2) follows L on ties; the upwind side is L iff
+// u* > 0 (as in the forward).
+template <typename T>
+__device__ __forceinline__ void face_flux_vjp(const FaceState<T>& L, const FaceState<T>& R,
+                                              T gamma, T inv_gm1, const Flux<T>& Fb,
+                                              FaceState<T>& Lb, FaceState<T>& Rb) {
+  T cl2 = gamma * L.p / L.r;
+  T cr2 = gamma * R.p / R.r;
+  bool aleft = cl2 >= cr2;
+  T a = sqrt(aleft ? cl2 : cr2);
+  T S = L.r + R.r;
+  T iS = T(1) / S;
+  T iS2 = iS * iS;
+  T B = L.r * R.r;
+  T Du = R.un - L.un;
+  T Dp = R.p - L.p;
+  T ps = (R.r * L.p + L.r * R.p) * iS - (B * iS) * a * Du;
+  T us = (L.r * L.un + R.r * R.un) * iS - iS * Dp / a;
+  bool left = us > T(0);
+  T r = left ? L.r : R.r;
+  T un = left ? L.un : R.un;
+  T ut = left ? L.ut : R.ut;
+  T p = left ? L.p : R.p;
+  T E = p * inv_gm1 + T(0.5) * r * (un * un + ut * ut);
+
+  // through eq. (12) and the upwind state
+  T Eb = Fb.f3 * us;
+  T usb = Fb.f0 * r + Fb.f1 * r * un + Fb.f2 * r * ut + Fb.f3 * (E + ps);
+  T psb = Fb.f1 + Fb.f3 * us;
+  T rb = Fb.f0 * us + Fb.f1 * us * un + Fb.f2 * us * ut + Eb * T(0.5) * (un * un + ut * ut);
+  T unb = Fb.f1 * r * us + Eb * r * un;
+  T utb = Fb.f2 * r * us + Eb * r * ut;
+  T pb = Eb * inv_gm1;
+
+  // through eqs. (13)-(14)
+  T ab = psb * (-B * iS * Du) + usb * (iS * Dp / (a * a));
+  T rlb = psb * (R.r * Dp * iS2 - R.r * R.r * iS2 * a * Du) + usb * (-R.r * Du * iS2 + Dp * iS2 / a);
+  T rrb = psb * (-L.r * Dp * iS2 - L.r * L.r * iS2 * a * Du) + usb * (L.r * Du * iS2 + Dp * iS2 / a);
+  T unlb = psb * (B * iS * a) + usb * (L.r * iS);
+  T unrb = psb * (-B * iS * a) + usb * (R.r * iS);
+  T plb = psb * (R.r * iS) + usb * (iS / a);
+  T prb = psb * (L.r * iS) - usb * (iS / a);
+  // a = sqrt(gamma p_s / rho_s): da/dp = a / (2p), da/drho = -a / (2 rho)
+  if (aleft) {
+    rlb += ab * (-a / (T(2) * L.r));
+    plb += ab * (a / (T(2) * L.p));
+  } else {
+    rrb += ab * (-a / (T(2) * R.r));
+    prb += ab * (a / (T(2) * R.p));
+  }
+  Lb.r = rlb + (left ? rb : T(0));
+  Lb.un = unlb + (left ? unb : T(0));
+  Lb.ut = left ? utb : T(0);
+  Lb.p = plb + (left ? pb : T(0));
+  Rb.r = rrb + (left ? T(0) : rb);
+  Rb.un = unrb + (left ? T(0) : unb);
+  Rb.ut = left ? T(0) : utb;
+  Rb.p = prb + (left ? T(0) : pb);
+}
+
+// ---- wave-level reductions --------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Hardware assigns workgroup b to die b % 8.  Remap so each die works on a
+// contiguous range of logical blocks (neighbouring tiles share halo rows
+// and columns through that die's L2).  nblk_pad is a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int nblk_pad) {
+  int per = nblk_pad / kXcds;
+  return (b % kXcds) * per + b / kXcds;
+}
+
+}  // namespace lf

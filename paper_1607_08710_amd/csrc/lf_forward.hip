@@ -1,0 +1,528 @@
+// lf_forward.hip -- forward kernels of the gfx950 Lagrange-flux library.
+//
+// One fused stage kernel per Heun stage (Sec. 5, predictor items 2-6 and
+// corrector items 7-11 of the paper's list), the CFL max-reduction
+// (item 1), the device-side control of the time loop and the
+// conservation totals.
+//
+// Stage kernel layout.  A wave of 64 lanes owns a strip of 64 consecutive
+// columns (x, the fastest index of the structure-of-arrays state) and
+// marches up kTileW-wide strips of `rows` rows.  Lanes 2..61 produce
+// output; lanes 0, 1, 62, 63 are the stencil halo and only feed their
+// neighbours.  x-neighbours are exchanged with DPP whole-wave shifts; the
+// y-direction keeps a register window (two primitive rows, one row of
+// y-slopes and differences, and the last y-face flux), so every face flux
+// is evaluated exactly once per wave and never written to memory.
+#include "lf_internal.h"
+
+namespace lf {
+
+template <typename T>
+struct StageArgs {
+  const T* in;    // stencil input state
+  const T* base;  // corrector: U^n (may alias out)
+  T* out;
+  Ctl* ctl;
+  int nx, ny;
+  int tiles_x, tiles_y, rows;
+  int blocks, blocks_pad;
+  long long plane;
+  T gamma, gm1, inv_gm1, beta, idx, idy;
+  double dt;
+  int dt_dev;
+  int reduce;
+};
+
+template <typename T>
+__device__ __forceinline__ Prim<T> sub(const Prim<T>& a, const Prim<T>& b) {
+  return {a.r - b.r, a.u - b.u, a.v - b.v, a.p - b.p};
+}
+
+template <typename T>
+__device__ __forceinline__ Prim<T> slope(const Prim<T>& dm, const Prim<T>& dp, T beta) {
+  return {sweby(dm.r, dp.r, beta), sweby(dm.u, dp.u, beta), sweby(dm.v, dp.v, beta),
+          sweby(dm.p, dp.p, beta)};
+}
+
+// w + s/2 in the x-face frame (u normal) or the y-face frame (v normal).
+template <typename T, bool YFACE>
+__device__ __forceinline__ FaceState<T> face_plus(const Prim<T>& w, const Prim<T>& s) {
+  T h = T(0.5);
+  T r = fma(h, s.r, w.r), u = fma(h, s.u, w.u), v = fma(h, s.v, w.v), p = fma(h, s.p, w.p);
+  if constexpr (YFACE) return {r, v, u, p};
+  else return {r, u, v, p};
+}
+template <typename T, bool YFACE>
+__device__ __forceinline__ FaceState<T> face_minus(const Prim<T>& w, const Prim<T>& s) {
+  T h = T(-0.5);
+  T r = fma(h, s.r, w.r), u = fma(h, s.u, w.u), v = fma(h, s.v, w.v), p = fma(h, s.p, w.p);
+  if constexpr (YFACE) return {r, v, u, p};
+  else return {r, u, v, p};
+}
+
+template <typename T>
+__device__ __forceinline__ Prim<T> shl1(const Prim<T>& w) {
+  return {shl1(w.r), shl1(w.u), shl1(w.v), shl1(w.p)};
+}
+template <typename T>
+__device__ __forceinline__ Prim<T> shr1(const Prim<T>& w) {
+  return {shr1(w.r), shr1(w.u), shr1(w.v), shr1(w.p)};
+}
+template <typename T>
+__device__ __forceinline__ Flux<T> shr1(const Flux<T>& f) {
+  return {shr1(f.f0), shr1(f.f1), shr1(f.f2), shr1(f.f3)};
+}
+
+// Combination of one stage in FP64: predictor U - dt R; corrector
+// (U^n + U* - dt R(U*)) / 2; residual mode writes R.
+template <int MODE, typename T>
+__device__ __forceinline__ T combine(T q, T b, T res, double dt) {
+  if constexpr (MODE == kResidual) {
+    return res;
+  } else if constexpr (MODE == kPredictor) {
+    return T(double(q) - dt * double(res));
+  } else {
+    return T(0.5 * (double(b) + (double(q) - dt * double(res))));
+  }
+}
+
+template <typename T, int MODE, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<T> a) {
+  if (a.dt_dev && a.ctl->done) return;
+  const int lb = xcd_block(blockIdx.x, a.blocks_pad);
+  if (lb >= a.blocks) return;
+  const int wave = lb * kWavesPerBlock + (threadIdx.x >> 6);
+  if (wave >= a.tiles_x * a.tiles_y) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ty = wave / a.tiles_x;
+  const int tx = wave - ty * a.tiles_x;
+  const int c = tx * kTileW - kHalo + lane;
+  const int cm = map_index<BCX>(c, a.nx);
+  const int y0 = ty * a.rows;
+  const int y1 = min(y0 + a.rows, a.ny);
+  const bool out_lane = lane >= kHalo && lane < kWave - kHalo && c < a.nx;
+  const double dt = a.dt_dev ? a.ctl->dt : a.dt;
+  const int nx = a.nx, ny = a.ny;
+  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta;
+
+  const T* __restrict__ I0 = a.in;
+  const T* __restrict__ I1 = I0 + a.plane;
+  const T* __restrict__ I2 = I1 + a.plane;
+  const T* __restrict__ I3 = I2 + a.plane;
+
+  auto load_row = [&](int row, T q[4]) {
+    const int off = map_index<BCY>(row, ny) * nx + cm;
+    q[0] = I0[off];
+    q[1] = I1[off];
+    q[2] = I2[off];
+    q[3] = I3[off];
+  };
+
+  // prologue: rows y0-2 .. y0+1, slopes sigma(y0-1), sigma(y0), face y0-1/2
+  T qa[4], qb[4], qo[4], qo1[4], qn[4];
+  load_row(y0 - 2, qa);
+  load_row(y0 - 1, qb);
+  load_row(y0, qo);
+  load_row(y0 + 1, qo1);
+  load_row(y0 + 2, qn);
+  Prim<T> wa = to_prim(qa[0], qa[1], qa[2], qa[3], gm1);
+  Prim<T> wb = to_prim(qb[0], qb[1], qb[2], qb[3], gm1);
+  Prim<T> wo = to_prim(qo[0], qo[1], qo[2], qo[3], gm1);
+  Prim<T> wo1 = to_prim(qo1[0], qo1[1], qo1[2], qo1[3], gm1);
+  Prim<T> d_lo = sub(wb, wa);   // y0 - 3/2
+  Prim<T> d_mid = sub(wo, wb);  // y0 - 1/2
+  Prim<T> d_o = sub(wo1, wo);   // y0 + 1/2
+  Prim<T> s_b = slope(d_lo, d_mid, beta);
+  Prim<T> s_o = slope(d_mid, d_o, beta);
+  Flux<T> Gp = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(wo, s_o), gam, igm1);
+
+  double smax = 0.0;
+  bool bad = false;
+
+  T* __restrict__ O0 = a.out;
+  T* __restrict__ O1 = O0 + a.plane;
+  T* __restrict__ O2 = O1 + a.plane;
+  T* __restrict__ O3 = O2 + a.plane;
+  const T* B0 = a.base;
+  const T* B1 = B0 + a.plane;
+  const T* B2 = B1 + a.plane;
+  const T* B3 = B2 + a.plane;
+
+  for (int o = y0; o < y1; ++o) {
+    T qnn[4];
+    if (o + 1 < y1) load_row(o + 3, qnn);
+    const int off = o * nx + cm;
+    T b[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (MODE == kCorrector) {
+      b[0] = B0[off];
+      b[1] = B1[off];
+      b[2] = B2[off];
+      b[3] = B3[off];
+    }
+
+    // y: new row o+2, slope of row o+1, flux through face o+1/2
+    Prim<T> wn = to_prim(qn[0], qn[1], qn[2], qn[3], gm1);
+    Prim<T> dn = sub(wn, wo1);
+    Prim<T> s_o1 = slope(d_o, dn, beta);
+    Flux<T> G = face_flux(face_plus<T, true>(wo, s_o), face_minus<T, true>(wo1, s_o1), gam, igm1);
+
+    // x: slopes of row o from lane neighbours, flux through face c+1/2
+    Prim<T> wr1 = shl1(wo);          // w_{c+1}
+    Prim<T> dxp = sub(wr1, wo);      // w_{c+1} - w_c
+    Prim<T> dxm = shr1(dxp);         // w_c - w_{c-1}
+    Prim<T> sx = slope(dxm, dxp, beta);
+    Prim<T> sx1 = shl1(sx);          // sigma_{c+1}
+    Flux<T> F = face_flux(face_plus<T, false>(wo, sx), face_minus<T, false>(wr1, sx1), gam, igm1);
+    Flux<T> Fm = shr1(F);            // flux through face c-1/2
+
+    // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11)
+    T r0 = (F.f0 - Fm.f0) * a.idx + (G.f0 - Gp.f0) * a.idy;
+    T r1 = (F.f1 - Fm.f1) * a.idx + (G.f2 - Gp.f2) * a.idy;
+    T r2 = (F.f2 - Fm.f2) * a.idx + (G.f1 - Gp.f1) * a.idy;
+    T r3 = (F.f3 - Fm.f3) * a.idx + (G.f3 - Gp.f3) * a.idy;
+
+    T u0 = combine<MODE>(qo[0], b[0], r0, dt);
+    T u1 = combine<MODE>(qo[1], b[1], r1, dt);
+    T u2 = combine<MODE>(qo[2], b[2], r2, dt);
+    T u3 = combine<MODE>(qo[3], b[3], r3, dt);
+    if (out_lane) {
+      O0[off] = u0;
+      O1[off] = u1;
+      O2[off] = u2;
+      O3[off] = u3;
+    }
+    if constexpr (MODE == kCorrector) {
+      if (a.reduce) {
+        // CFL wave speed of the new state, (|u|+c)/dx + (|v|+c)/dy
+        Prim<T> w = to_prim(u0, u1, u2, u3, gm1);
+        T cs = sqrt(gam * w.p / w.r);
+        T s = (fabs(w.u) + cs) * a.idx + (fabs(w.v) + cs) * a.idy;
+        bool ok = (w.r > T(0)) && (w.p > T(0)) && (s <= T(3.0e38));
+        if (out_lane) {
+          if (ok) smax = fmax(smax, double(s));
+          else bad = true;
+        }
+      }
+    }
+
+    // slide the window one row up
+    Gp = G;
+    wo = wo1;
+    wo1 = wn;
+    s_o = s_o1;
+    d_o = dn;
+    for (int k = 0; k < 4; ++k) {
+      qo[k] = qo1[k];
+      qo1[k] = qn[k];
+      qn[k] = qnn[k];
+    }
+  }
+
+  if constexpr (MODE == kCorrector) {
+    if (a.reduce) {
+      unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(smax));
+      unsigned long long anybad = __ballot(bad);
+      if (lane == 0) {
+        if (m) atomicMax(&a.ctl->smax, m);
+        if (anybad) atomicOr(&a.ctl->flag, 1u);
+      }
+    }
+  }
+}
+
+// ---- standalone CFL reduction (lf_dt, start of lf_advance) ----------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void wavespeed_kernel(const T* __restrict__ U, long long plane,
+                                                        T gamma, T gm1, T idx, T idy, Ctl* ctl) {
+  double smax = 0.0;
+  bool bad = false;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride) {
+    T q0 = U[q], q1 = U[plane + q], q2 = U[2 * plane + q], q3 = U[3 * plane + q];
+    Prim<T> w = to_prim(q0, q1, q2, q3, gm1);
+    T cs = sqrt(gamma * w.p / w.r);
+    T s = (fabs(w.u) + cs) * idx + (fabs(w.v) + cs) * idy;
+    bool ok = (w.r > T(0)) && (w.p > T(0)) && (s <= T(3.0e38));
+    if (ok) smax = fmax(smax, double(s));
+    else bad = true;
+  }
+  unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(smax));
+  unsigned long long anybad = __ballot(bad);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (m) atomicMax(&ctl->smax, m);
+    if (anybad) atomicOr(&ctl->flag, 1u);
+  }
+}
+
+// ---- time-loop control (single thread) -----------------------------------
+
+__global__ void ctl_init_kernel(Ctl* c, double t0, double t_end, long long max_steps, double cfl) {
+  c->smax = 0ull;
+  c->flag = 0u;
+  c->done = (t0 < t_end && max_steps > 0) ? 0u : 1u;
+  c->dt = 0.0;
+  c->t = t0;
+  c->t_end = t_end;
+  c->step = 0;
+  c->max_steps = max_steps;
+  c->cfl = cfl;
+  c->clamped = 0u;
+}
+
+// dt of the next step from the reduced wave speed, clamped to t_end.
+__device__ void ctl_next_dt(Ctl* c) {
+  double s = __longlong_as_double((long long)c->smax);
+  c->smax = 0ull;
+  if (c->flag || !(s > 0.0)) {
+    c->flag |= 1u;
+    c->done = 1u;
+    c->dt = 0.0;
+    return;
+  }
+  double dt = c->cfl / s;
+  double rem = c->t_end - c->t;
+  c->clamped = 0u;
+  if (dt >= rem) {
+    dt = rem;
+    c->clamped = 1u;
+  }
+  c->dt = dt;
+}
+
+// dt of the first step.  When the loop is empty (t0 >= t_end or no steps
+// allowed) only the non-physical flag of the initial state is kept.
+__global__ void ctl_first_kernel(Ctl* c) {
+  if (c->done) return;
+  ctl_next_dt(c);
+}
+
+__global__ void ctl_step_kernel(Ctl* c) {
+  if (c->done) return;
+  c->t = c->clamped ? c->t_end : c->t + c->dt;
+  c->dt_hist[c->step % kDtHist] = c->dt;
+  c->step += 1;
+  if (c->flag) {
+    c->done = 1u;
+    return;
+  }
+  if (!(c->t < c->t_end) || c->step >= c->max_steps) {
+    c->done = 1u;
+    return;
+  }
+  ctl_next_dt(c);
+}
+
+// ---- deterministic compensated totals -----------------------------------------
+
+struct Acc {
+  double s, c;
+};
+
+__device__ __forceinline__ Acc acc_add(Acc a, double x) {
+  double t = a.s + x;
+  double e = (fabs(a.s) >= fabs(x)) ? ((a.s - t) + x) : ((x - t) + a.s);
+  return {t, a.c + e};
+}
+__device__ __forceinline__ Acc acc_merge(Acc a, Acc b) {
+  Acc r = acc_add(a, b.s);
+  r.c += b.c;
+  return r;
+}
+
+template <int NT>
+__device__ void block_merge(Acc (&v)[4], Acc (*sh)[NT]) {
+  for (int f = 0; f < 4; ++f) sh[f][threadIdx.x] = v[f];
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int f = 0; f < 4; ++f) sh[f][threadIdx.x] = acc_merge(sh[f][threadIdx.x], sh[f][threadIdx.x + w]);
+    __syncthreads();
+  }
+  for (int f = 0; f < 4; ++f) v[f] = sh[f][0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void totals_partial_kernel(const T* __restrict__ U, long long plane,
+                                                             double* __restrict__ part) {
+  __shared__ Acc sh[4][256];
+  Acc v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride)
+    for (int f = 0; f < 4; ++f) v[f] = acc_add(v[f], double(U[f * plane + q]));
+  block_merge<256>(v, sh);
+  if (threadIdx.x == 0)
+    for (int f = 0; f < 4; ++f) {
+      part[(blockIdx.x * 4 + f) * 2 + 0] = v[f].s;
+      part[(blockIdx.x * 4 + f) * 2 + 1] = v[f].c;
+    }
+}
+
+__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ part, int nblk,
+                                                           double area, Ctl* ctl) {
+  __shared__ Acc sh[4][256];
+  Acc v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (int f = 0; f < 4; ++f)
+      v[f] = acc_merge(v[f], Acc{part[(b * 4 + f) * 2], part[(b * 4 + f) * 2 + 1]});
+  block_merge<256>(v, sh);
+  if (threadIdx.x == 0)
+    for (int f = 0; f < 4; ++f) ctl->totals[f] = (v[f].s + v[f].c) * area;
+}
+
+// ---- host launchers -----------------------------------------------------------
+
+template <typename T, int MODE, int BCX, int BCY>
+static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base, void* out, double dt,
+                                 Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
+  StageArgs<T> a;
+  a.in = static_cast<const T*>(in);
+  a.base = static_cast<const T*>(base);
+  a.out = static_cast<T*>(out);
+  a.ctl = ctl;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.tiles_x = g.tiles_x;
+  a.tiles_y = g.tiles_y;
+  a.rows = g.rows_per_wave;
+  a.blocks = g.blocks;
+  a.blocks_pad = g.blocks_pad;
+  a.plane = (long long)g.nx * g.ny;
+  a.gamma = T(g.gamma);
+  a.gm1 = T(g.gamma - 1.0);
+  a.inv_gm1 = T(1.0 / (g.gamma - 1.0));
+  a.beta = T(g.beta);
+  a.idx = T(1.0 / g.dx);
+  a.idy = T(1.0 / g.dy);
+  a.dt = dt;
+  a.dt_dev = dt_dev ? 1 : 0;
+  a.reduce = reduce ? 1 : 0;
+  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY>), dim3(g.blocks_pad), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+static hipError_t launch_stage_bc(const Grid& g, const void* in, const void* base, void* out, double dt,
+                                  Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
+  if (g.bc_x == kBcPeriodic) {
+    if (g.bc_y == kBcPeriodic)
+      return launch_stage_t<T, MODE, kBcPeriodic, kBcPeriodic>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    return launch_stage_t<T, MODE, kBcPeriodic, kBcTransmissive>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+  }
+  if (g.bc_y == kBcPeriodic)
+    return launch_stage_t<T, MODE, kBcTransmissive, kBcPeriodic>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+  return launch_stage_t<T, MODE, kBcTransmissive, kBcTransmissive>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+}
+
+template <typename T>
+static hipError_t launch_stage_mode(const Grid& g, int mode, const void* in, const void* base, void* out,
+                                    double dt, Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
+  switch (mode) {
+    case kResidual: return launch_stage_bc<T, kResidual>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case kPredictor: return launch_stage_bc<T, kPredictor>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    default: return launch_stage_bc<T, kCorrector>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+  }
+}
+
+hipError_t launch_stage(const Grid& g, int mode, const void* in, const void* base, void* out, double dt,
+                        Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
+  if (g.dtype == 0) return launch_stage_mode<double>(g, mode, in, base, out, dt, ctl, dt_dev, reduce, s);
+  return launch_stage_mode<float>(g, mode, in, base, out, dt, ctl, dt_dev, reduce, s);
+}
+
+static int reduction_blocks(long long plane) {
+  long long b = (plane + 255) / 256;
+  if (b > 2048) b = 2048;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_wavespeed(const Grid& g, const void* U, Ctl* ctl, hipStream_t s) {
+  const long long plane = (long long)g.nx * g.ny;
+  const int nb = reduction_blocks(plane);
+  if (g.dtype == 0)
+    hipLaunchKernelGGL(wavespeed_kernel<double>, dim3(nb), dim3(256), 0, s, static_cast<const double*>(U),
+                       plane, g.gamma, g.gamma - 1.0, 1.0 / g.dx, 1.0 / g.dy, ctl);
+  else
+    hipLaunchKernelGGL(wavespeed_kernel<float>, dim3(nb), dim3(256), 0, s, static_cast<const float*>(U),
+                       plane, float(g.gamma), float(g.gamma - 1.0), float(1.0 / g.dx), float(1.0 / g.dy), ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_init(Ctl* ctl, double t0, double t_end, long long max_steps, double cfl,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, ctl, t0, t_end, max_steps, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_first(Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_first_kernel, dim3(1), dim3(1), 0, s, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_step(Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(ctl_step_kernel, dim3(1), dim3(1), 0, s, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const Grid& g, const Layout& L, const void* U, void* ws, hipStream_t s) {
+  const long long plane = (long long)g.nx * g.ny;
+  char* w = static_cast<char*>(ws);
+  double* part = reinterpret_cast<double*>(w + L.partials);
+  Ctl* ctl = reinterpret_cast<Ctl*>(w + L.ctl);
+  if (g.dtype == 0)
+    hipLaunchKernelGGL(totals_partial_kernel<double>, dim3(L.totals_blocks), dim3(256), 0, s,
+                       static_cast<const double*>(U), plane, part);
+  else
+    hipLaunchKernelGGL(totals_partial_kernel<float>, dim3(L.totals_blocks), dim3(256), 0, s,
+                       static_cast<const float*>(U), plane, part);
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, s, part, L.totals_blocks, g.dx * g.dy, ctl);
+  return hipGetLastError();
+}
+
+// ---- grid / workspace planning ------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, double beta, int bc_x,
+               int bc_y, int dtype) {
+  Grid g;
+  g.nx = nx;
+  g.ny = ny;
+  g.dx = dx;
+  g.dy = dy;
+  g.gamma = gamma;
+  g.cfl = cfl;
+  g.beta = beta;
+  g.bc_x = bc_x;
+  g.bc_y = bc_y;
+  g.dtype = dtype;
+  g.tiles_x = (nx + kTileW - 1) / kTileW;
+  // Rows per wave: long strips amortise the 4 halo rows; keep at least
+  // ~8 waves per SIMD (256 CUs x 4 SIMDs) in flight for latency hiding.
+  const long long target_waves = 8192;
+  long long rows = (long long)g.tiles_x * ny / target_waves;
+  int r = 16;
+  while (r < 256 && 2 * r <= rows) r *= 2;
+  if (r > ny) r = ny;
+  g.rows_per_wave = r;
+  g.tiles_y = (ny + r - 1) / r;
+  const long long waves = (long long)g.tiles_x * g.tiles_y;
+  g.blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  g.blocks_pad = (g.blocks + kXcds - 1) / kXcds * kXcds;
+  return g;
+}
+
+Layout make_layout(const Grid& g) {
+  Layout L;
+  const size_t esz = g.dtype == 0 ? sizeof(double) : sizeof(float);
+  const size_t state = 4 * (size_t)g.nx * (size_t)g.ny * esz;
+  L.totals_blocks = reduction_blocks((long long)g.nx * g.ny);
+  L.ustar = 0;
+  L.mu = align256(L.ustar + state);
+  L.ctl = align256(L.mu + state);
+  L.partials = align256(L.ctl + sizeof(Ctl));
+  L.total = align256(L.partials + (size_t)L.totals_blocks * 8 * sizeof(double));
+  return L;
+}
+
+}  // namespace lf

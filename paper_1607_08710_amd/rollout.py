@@ -1,0 +1,73 @@
+"""Differentiable rollout of N Heun steps at frozen time steps, with
+checkpoint-and-recompute over the time steps.
+
+Forward: N calls of ``lf_step`` with the given dts; the state at every
+``ckpt_every``-th step is kept (those are the outputs of the step calls,
+not copies).  Backward: for each segment, last to first, the segment's
+states are recomputed from its checkpoint with ``lf_step`` and the adjoint
+is carried back through it with ``lf_adjoint_step`` (the discrete adjoint
+of the step map, recomputing U* from U^n inside the library).
+
+Peak device memory: the checkpoints plus one segment of states.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import torch
+
+
+class LagrangeFluxRollout(torch.autograd.Function):
+    """U_N = S_{dt_{N-1}} o ... o S_{dt_0} (U_0), differentiable in U_0."""
+
+    @staticmethod
+    def forward(ctx, U0: torch.Tensor, solver, dts: Sequence[float], ckpt_every: int = 20):
+        dts = [float(d) for d in dts]
+        C = max(1, int(ckpt_every))
+        ckpts = [U0.detach()]
+        U = U0.detach()
+        A, B = solver.empty_state(), solver.empty_state()  # ping-pong for the other steps
+        for n, dt in enumerate(dts):
+            last = n + 1 == len(dts)
+            keep = ((n + 1) % C == 0) and not last
+            if keep or last:
+                out = solver.empty_state()
+            else:
+                out = A if U is not A else B
+            solver.step(U, out, dt)
+            if keep:
+                ckpts.append(out)
+            U = out
+        if not dts:
+            U = U0.detach().clone()
+        ctx.solver = solver
+        ctx.dts = dts
+        ctx.C = C
+        ctx.save_for_backward(*ckpts)
+        return U
+
+    @staticmethod
+    def backward(ctx, gN: torch.Tensor):
+        solver, dts, C = ctx.solver, ctx.dts, ctx.C
+        ckpts = ctx.saved_tensors
+        lam = gN.contiguous().to(solver.torch_dtype)
+        N = len(dts)
+        nseg = len(ckpts)
+        lam_next = torch.empty_like(lam)
+        for s in reversed(range(nseg)):
+            n0 = s * C
+            n1 = min(N, n0 + C)
+            states = [ckpts[s]]
+            for n in range(n0, n1 - 1):
+                out = solver.empty_state()
+                solver.step(states[-1], out, dts[n])
+                states.append(out)
+            for n in reversed(range(n0, n1)):
+                solver.adjoint_step(states[n - n0], dts[n], lam, lam_next)
+                lam, lam_next = lam_next, lam
+            del states
+        return lam, None, None, None
+
+
+def rollout(U0: torch.Tensor, solver, dts: Sequence[float], ckpt_every: int = 20) -> torch.Tensor:
+    return LagrangeFluxRollout.apply(U0, solver, dts, ckpt_every)

@@ -223,3 +223,26 @@ def random_state(nx: int, ny: int, seed: int, *, gamma: float = 1.4, rough: bool
         v = 0.5 * np.cos(2 * math.pi * (x - y) + ph[3]) + 0.01 * rng.standard_normal((ny, nx))
         p = 1.0 + 0.2 * np.cos(2 * math.pi * x) * np.sin(2 * math.pi * y)
     return prim_to_cons(gamma, rho, u, v, p)
+
+
+def kelvin_helmholtz_torch(n: int, *, device="cuda", dtype=None, gamma: float = 1.4):
+    """The Kelvin-Helmholtz state of kelvin_helmholtz(), built with torch
+    directly in device memory (for the large benchmark grids).  Computed in
+    float64 and cast once to ``dtype``."""
+    import torch
+    dtype = dtype or torch.float64
+    x = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) / n
+    inner = torch.abs(x - 0.5) < 0.25
+    rho_y = torch.where(inner, 2.0, 1.0)
+    u_y = torch.where(inner, 0.5, -0.5)
+    v_x = 0.01 * torch.sin(4.0 * math.pi * x)
+    U = torch.empty((4, n, n), dtype=dtype, device=device)
+    rho = rho_y[:, None].expand(n, n)
+    u = u_y[:, None].expand(n, n)
+    v = v_x[None, :].expand(n, n)
+    U[0] = rho
+    U[1] = rho * u
+    U[2] = rho * v
+    U[3] = 2.5 / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    cfg = _cfg(n, n, 1.0, 1.0, PERIODIC, PERIODIC, gamma, 0.5, 1.5, steps=500)
+    return U, cfg
