@@ -58,9 +58,9 @@ typedef struct {
     double dx, dy;    /* uniform cell sizes, > 0                                */
     double gamma;     /* ratio of specific heats, in (1, 3] (Sec. 3)            */
     double cfl;       /* CFL number, > 0 (Heun list, item 1)                    */
-    double beta;      /* Sweby coefficient, in [0, 2]; the paper's range for
-                         second order is [1, 2] (eq. (sweby)); 0 gives the
-                         first-order scheme                                     */
+    double beta;      /* Sweby coefficient: 1 <= beta <= 2, the paper's range
+                         for second order (eq. (sweby)), or 0 for the
+                         first-order scheme; other values are LF_ERR_ARG    */
     int32_t bc_x;     /* lf_bc along x: periodic wraps the index, transmissive
                          clamps it (ghost cells copy the edge cell)             */
     int32_t bc_y;     /* lf_bc along y                                          */

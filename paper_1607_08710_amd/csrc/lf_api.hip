@@ -27,7 +27,7 @@ bool params_ok(const lf_params* p) {
   if ((long long)p->nx * (long long)p->ny >= (1LL << 31)) return false;
   if (!(p->dx > 0.0) || !(p->dy > 0.0) || !isfinite(p->dx) || !isfinite(p->dy)) return false;
   if (!(p->gamma > 1.0 && p->gamma <= 3.0)) return false;
-  if (!(p->beta >= 0.0 && p->beta <= 2.0)) return false;
+  if (!(p->beta == 0.0 || (p->beta >= 1.0 && p->beta <= 2.0))) return false;
   if (!(p->cfl > 0.0) || !isfinite(p->cfl)) return false;
   if (p->bc_x != LF_BC_PERIODIC && p->bc_x != LF_BC_TRANSMISSIVE) return false;
   if (p->bc_y != LF_BC_PERIODIC && p->bc_y != LF_BC_TRANSMISSIVE) return false;

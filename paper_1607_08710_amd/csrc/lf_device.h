@@ -17,8 +17,11 @@ namespace lf {
 constexpr int kWave = 64;        // wavefront width on CDNA
 constexpr int kHalo = 2;         // stencil half-width along each axis
 constexpr int kTileW = kWave - 2 * kHalo;  // output columns per wave (60)
-constexpr int kWavesPerBlock = 4;
-constexpr int kBlock = kWave * kWavesPerBlock;
+// Waves per stage-kernel block: the block's tiles cover 60 * waves
+// consecutive columns, i.e. exactly 15 cache lines of 128 bytes in either
+// precision (240 doubles or 480 floats), so its stores can be line-aligned.
+template <typename T>
+constexpr int waves_per_block() { return sizeof(T) == 8 ? 4 : 8; }
 constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kDtHist = 4096;    // per-step dt records kept on the device
 
@@ -60,11 +63,11 @@ __device__ __forceinline__ int map_index(int k, int n) {
 
 // Lane l receives the value of lane l-1 (lane 0 receives 0).
 __device__ __forceinline__ int shr1_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 // Lane l receives the value of lane l+1 (lane 63 receives 0).
 __device__ __forceinline__ int shl1_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
 }
 
 __device__ __forceinline__ double shr1(double v) {
@@ -82,6 +85,31 @@ __device__ __forceinline__ float shl1(float v) {
   return __int_as_float(shl1_i(__float_as_int(v)));
 }
 
+// ---- reciprocal and reciprocal square root -------------------------------
+//
+// FP64: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by two
+// Newton steps, which lands within an ulp of the rounded quotient -- far
+// cheaper than the IEEE division and square-root sequences.  FP32: the
+// hardware instruction alone (1 ulp).
+
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double rsq(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * r, r, 1.0);  // 1 - x r^2
+  r = fma(0.5 * r, e, r);
+  e = fma(-x * r, r, 1.0);
+  return fma(0.5 * r, e, r);
+}
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // ---- primitive variables (perfect gas, Sec. 3) -----------------------------
 
 template <typename T>
@@ -92,7 +120,7 @@ struct Prim {
 template <typename T>
 __device__ __forceinline__ Prim<T> to_prim(T q0, T q1, T q2, T q3, T gm1) {
   Prim<T> w;
-  T ir = T(1) / q0;
+  T ir = rcp(q0);
   w.r = q0;
   w.u = q1 * ir;
   w.v = q2 * ir;
@@ -104,11 +132,19 @@ __device__ __forceinline__ Prim<T> to_prim(T q0, T q1, T q2, T q3, T gm1) {
 
 // ---- Sweby limiter, eq. (sweby) ---------------------------------------------
 
+// For beta >= 1 the max-min of eq. (sweby) equals min(beta min(|a|,|b|),
+// max(|a|,|b|)) bit for bit (each minimum is taken against a value at least
+// as large as the other argument), and for beta = 0 both give 0.  The
+// library accepts beta = 0 or 1 <= beta <= 2.  With bs = b sign(a), a
+// negative bs (ab < 0) makes the result negative before the max with 0,
+// so one expression also covers the ab <= 0 branch.  The result carries
+// the sign of a.
 template <typename T>
 __device__ __forceinline__ T sweby(T a, T b, T beta) {
-  T aa = fabs(a), ab = fabs(b);
-  T m = fmax(fmin(aa, beta * ab), fmin(beta * aa, ab));
-  return (a * b > T(0)) ? copysign(m, a) : T(0);
+  const T bs = copysign(T(1), a) * b;
+  const T aa = fabs(a);
+  const T m = fmin(beta * fmin(aa, bs), fmax(aa, bs));
+  return copysign(fmax(m, T(0)), a);
 }
 
 // Partial derivatives of sweby(a, b) with the conventions: zero when
@@ -147,27 +183,32 @@ struct Flux {
 template <typename T>
 __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceState<T>& R,
                                              T gamma, T inv_gm1) {
-  // a = max(c_L, c_R) = sqrt(max(gamma p_L / rho_L, gamma p_R / rho_R))
-  T cl2 = gamma * L.p / L.r;
-  T cr2 = gamma * R.p / R.r;
-  T a = sqrt(fmax(cl2, cr2));
-  T S = L.r + R.r;
-  T iS = T(1) / S;
+  // a = max(c_L, c_R): the side with the larger p/rho (compared as
+  // p_L rho_R >= p_R rho_L, both densities positive) sets a^2 = gamma p/rho.
+  const bool lside = L.p * R.r >= R.p * L.r;
+  const T ps_ = lside ? L.p : R.p;
+  const T rs_ = lside ? L.r : R.r;
+  const T S = L.r + R.r;
+  const T q = rcp(rs_ * S);          // 1 / (rho_s S)
+  const T iS = rs_ * q;              // 1 / S
+  const T a2 = gamma * ps_ * (S * q);  // gamma p_s / rho_s
+  const T ia = rsq(a2);              // 1 / a
+  const T a = a2 * ia;
   // eq. (13): p* = (rho_R p_L + rho_L p_R)/S - (rho_L rho_R / S) a (u_R - u_L)
-  T ps = (R.r * L.p + L.r * R.p) * iS - (L.r * R.r * iS) * a * (R.un - L.un);
+  const T ps = fma(-(L.r * R.r * iS) * a, R.un - L.un, fma(R.r, L.p, L.r * R.p) * iS);
   // eq. (14): u* = (rho_L u_L + rho_R u_R)/S - (p_R - p_L)/(S a)
-  T us = (L.r * L.un + R.r * R.un) * iS - iS * (R.p - L.p) / a;
+  const T us = fma(-(R.p - L.p), iS * ia, fma(L.r, L.un, R.r * R.un) * iS);
   // upwind on the sign of u*: left when u* > 0
-  bool left = us > T(0);
-  T r = left ? L.r : R.r;
-  T un = left ? L.un : R.un;
-  T ut = left ? L.ut : R.ut;
-  T p = left ? L.p : R.p;
-  T E = p * inv_gm1 + T(0.5) * r * (un * un + ut * ut);
-  T m = r * us;
+  const bool left = us > T(0);
+  const T r = left ? L.r : R.r;
+  const T un = left ? L.un : R.un;
+  const T ut = left ? L.ut : R.ut;
+  const T p = left ? L.p : R.p;
+  const T E = fma(T(0.5) * r, fma(un, un, ut * ut), p * inv_gm1);  // rho E of the upwind state
+  const T m = r * us;
   Flux<T> F;
   F.f0 = m;
-  F.f1 = m * un + ps;
+  F.f1 = fma(m, un, ps);
   F.f2 = m * ut;
   F.f3 = (E + ps) * us;
   return F;

@@ -25,9 +25,9 @@ struct StageArgs {
   Ctl* ctl;
   int nx, ny;
   int tiles_x, tiles_y, rows;
-  int blocks, blocks_pad;
+  int blocks_x, blocks, blocks_pad;
   long long plane;
-  T gamma, gm1, inv_gm1, beta, idx, idy;
+  T gamma, gm1, inv_gm1, beta, idx, idy, kxy;  // kxy = dx / dy
   double dt;
   int dt_dev;
   int reduce;
@@ -87,18 +87,22 @@ __device__ __forceinline__ T combine(T q, T b, T res, double dt) {
 }
 
 template <typename T, int MODE, int BCX, int BCY>
-__global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<T> a) {
+__global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(StageArgs<T> a) {
+  constexpr int WPB = waves_per_block<T>();
   if (a.dt_dev && a.ctl->done) return;
   const int lb = xcd_block(blockIdx.x, a.blocks_pad);
-  if (lb >= a.blocks) return;
-  const int wave = lb * kWavesPerBlock + (threadIdx.x >> 6);
-  if (wave >= a.tiles_x * a.tiles_y) return;
+  if (lb >= a.blocks) return;  // whole block
+  // block (bx, by): tiles bx*WPB .. bx*WPB+WPB-1 of row band by; a tile
+  // past the right edge still runs (the block synchronises every row) but
+  // stores nothing
+  const int by = lb / a.blocks_x;
+  const int bx = lb - by * a.blocks_x;
+  const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & (kWave - 1);
-  const int ty = wave / a.tiles_x;
-  const int tx = wave - ty * a.tiles_x;
+  const int tx = bx * WPB + w;
   const int c = tx * kTileW - kHalo + lane;
   const int cm = map_index<BCX>(c, a.nx);
-  const int y0 = ty * a.rows;
+  const int y0 = by * a.rows;
   const int y1 = min(y0 + a.rows, a.ny);
   const bool out_lane = lane >= kHalo && lane < kWave - kHalo && c < a.nx;
   const double dt = a.dt_dev ? a.ctl->dt : a.dt;
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<T> a) {
   const T* __restrict__ I2 = I1 + a.plane;
   const T* __restrict__ I3 = I2 + a.plane;
 
-  auto load_row = [&](int row, T q[4]) {
+  auto load_row = [&](int row, T (&q)[4]) {
     const int off = map_index<BCY>(row, ny) * nx + cm;
     q[0] = I0[off];
     q[1] = I1[off];
@@ -118,104 +122,170 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs<T> a) {
     q[3] = I3[off];
   };
 
-  // prologue: rows y0-2 .. y0+1, slopes sigma(y0-1), sigma(y0), face y0-1/2
-  T qa[4], qb[4], qo[4], qo1[4], qn[4];
-  load_row(y0 - 2, qa);
-  load_row(y0 - 1, qb);
-  load_row(y0, qo);
-  load_row(y0 + 1, qo1);
-  load_row(y0 + 2, qn);
-  Prim<T> wa = to_prim(qa[0], qa[1], qa[2], qa[3], gm1);
-  Prim<T> wb = to_prim(qb[0], qb[1], qb[2], qb[3], gm1);
-  Prim<T> wo = to_prim(qo[0], qo[1], qo[2], qo[3], gm1);
-  Prim<T> wo1 = to_prim(qo1[0], qo1[1], qo1[2], qo1[3], gm1);
-  Prim<T> d_lo = sub(wb, wa);   // y0 - 3/2
-  Prim<T> d_mid = sub(wo, wb);  // y0 - 1/2
-  Prim<T> d_o = sub(wo1, wo);   // y0 + 1/2
-  Prim<T> s_b = slope(d_lo, d_mid, beta);
-  Prim<T> s_o = slope(d_mid, d_o, beta);
-  Flux<T> Gp = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(wo, s_o), gam, igm1);
-
-  double smax = 0.0;
-  bool bad = false;
-
-  T* __restrict__ O0 = a.out;
-  T* __restrict__ O1 = O0 + a.plane;
-  T* __restrict__ O2 = O1 + a.plane;
-  T* __restrict__ O3 = O2 + a.plane;
+  T* O0 = a.out;
+  T* O1 = O0 + a.plane;
+  T* O2 = O1 + a.plane;
+  T* O3 = O2 + a.plane;
+  // base is nullptr unless MODE == kCorrector; only the corrector reads it
   const T* B0 = a.base;
   const T* B1 = B0 + a.plane;
   const T* B2 = B1 + a.plane;
   const T* B3 = B2 + a.plane;
 
-  for (int o = y0; o < y1; ++o) {
-    T qnn[4];
-    if (o + 1 < y1) load_row(o + 3, qnn);
-    const int off = o * nx + cm;
-    T b[4] = {T(0), T(0), T(0), T(0)};
-    if constexpr (MODE == kCorrector) {
-      b[0] = B0[off];
-      b[1] = B1[off];
-      b[2] = B2[off];
-      b[3] = B3[off];
-    }
+  // Row pipeline.  While row o is finished, the stencil rows o+3 and o+4
+  // are in flight (prefetch distance two rows) and the corrector's U^n rows
+  // o+1 and o+2 likewise.  The conservative values of rows o .. o+2, needed
+  // only for the stage combination, wait in a per-wave LDS ring (each lane
+  // reads back its own values, so no synchronisation is needed).  Slots
+  // alternate between the even and odd rows of a strip; the loop is
+  // unrolled by two so that they rotate by renaming.
+  __shared__ T ring[WPB][3][4][kWave];
+  T(*my)[4][kWave] = ring[w];
+  // Output staging: the block's WPB * 60 new values of a row are gathered
+  // in LDS (double buffered) and written back as whole 128-byte lines
+  // starting at the block's first column, a multiple of 15 lines.
+  constexpr int BW = WPB * kTileW;
+  __shared__ T obuf[2][4][BW];
+  const int xb = bx * BW;   // first column of the block
+  const int kst = w * kWave + lane;  // column (in the block) this lane stores
+  int par = 0;
+  auto ring_put = [&](int row, const T (&q)[4]) {
+    const int sl = row % 3;
+    my[sl][0][lane] = q[0];
+    my[sl][1][lane] = q[1];
+    my[sl][2][lane] = q[2];
+    my[sl][3][lane] = q[3];
+  };
 
-    // y: new row o+2, slope of row o+1, flux through face o+1/2
-    Prim<T> wn = to_prim(qn[0], qn[1], qn[2], qn[3], gm1);
-    Prim<T> dn = sub(wn, wo1);
-    Prim<T> s_o1 = slope(d_o, dn, beta);
-    Flux<T> G = face_flux(face_plus<T, true>(wo, s_o), face_minus<T, true>(wo1, s_o1), gam, igm1);
+  T QA[4], QB[4], BA[4] = {T(0), T(0), T(0), T(0)}, BB[4] = {T(0), T(0), T(0), T(0)};
+  Prim<T> W0, W1, Sg0, Sg1;
+  Flux<T> Gf0, Gf1;
+  {
+    T qa[4], qb[4], q0[4], q1[4];
+    load_row(y0 - 2, qa);
+    load_row(y0 - 1, qb);
+    load_row(y0, q0);
+    load_row(y0 + 1, q1);
+    load_row(y0 + 2, QA);
+    load_row(y0 + 3, QB);
+    if constexpr (MODE == kCorrector) {
+      const int o0 = y0 * nx + cm;
+      BA[0] = B0[o0];
+      BA[1] = B1[o0];
+      BA[2] = B2[o0];
+      BA[3] = B3[o0];
+      if (y0 + 1 < y1) {
+        const int o1 = o0 + nx;
+        BB[0] = B0[o1];
+        BB[1] = B1[o1];
+        BB[2] = B2[o1];
+        BB[3] = B3[o1];
+      }
+    }
+    Prim<T> wa = to_prim(qa[0], qa[1], qa[2], qa[3], gm1);
+    Prim<T> wb = to_prim(qb[0], qb[1], qb[2], qb[3], gm1);
+    W0 = to_prim(q0[0], q0[1], q0[2], q0[3], gm1);
+    W1 = to_prim(q1[0], q1[1], q1[2], q1[3], gm1);
+    ring_put(y0, q0);
+    ring_put(y0 + 1, q1);
+    Prim<T> d_lo = sub(wb, wa);    // y0 - 3/2
+    Prim<T> d_mid = sub(W0, wb);   // y0 - 1/2
+    Prim<T> s_b = slope(d_lo, d_mid, beta);
+    Sg0 = slope(d_mid, sub(W1, W0), beta);
+    Gf0 = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(W0, Sg0), gam, igm1);
+  }
+
+  double smax = 0.0;
+  bool bad = false;
+
+  // Row o: qc holds row o+2 (arrived) and then receives row o+4; bc holds
+  // U^n of row o and then receives row o+2; wo/wo1 are the primitive rows
+  // o and o+1 (wo is overwritten with row o+2); so/so1 the y-slopes of rows
+  // o and o+1; Gp/G the fluxes through the y-faces o-1/2 and o+1/2.
+  auto row = [&](int o, T (&qc)[4], T (&bc)[4], Prim<T>& wo, const Prim<T>& wo1, const Prim<T>& so,
+                 Prim<T>& so1, const Flux<T>& Gp, Flux<T>& G) {
+    const int off = o * nx + cm;
+    const Prim<T> wn = to_prim(qc[0], qc[1], qc[2], qc[3], gm1);
+    ring_put(o + 2, qc);
+    if (o + 3 <= y1) load_row(o + 4, qc);
+
+    // y: slope of row o+1, flux through face o+1/2
+    const Prim<T> dlo = sub(wo1, wo);
+    so1 = slope(dlo, sub(wn, wo1), beta);
+    G = face_flux(face_plus<T, true>(wo, so), face_minus<T, true>(wo1, so1), gam, igm1);
 
     // x: slopes of row o from lane neighbours, flux through face c+1/2
-    Prim<T> wr1 = shl1(wo);          // w_{c+1}
-    Prim<T> dxp = sub(wr1, wo);      // w_{c+1} - w_c
-    Prim<T> dxm = shr1(dxp);         // w_c - w_{c-1}
-    Prim<T> sx = slope(dxm, dxp, beta);
-    Prim<T> sx1 = shl1(sx);          // sigma_{c+1}
-    Flux<T> F = face_flux(face_plus<T, false>(wo, sx), face_minus<T, false>(wr1, sx1), gam, igm1);
-    Flux<T> Fm = shr1(F);            // flux through face c-1/2
+    const Prim<T> wr1 = shl1(wo);       // w_{c+1}
+    const Prim<T> dxp = sub(wr1, wo);   // w_{c+1} - w_c
+    const Prim<T> dxm = shr1(dxp);      // w_c - w_{c-1}
+    const Prim<T> sx = slope(dxm, dxp, beta);
+    const Prim<T> sx1 = shl1(sx);       // sigma_{c+1}
+    const Flux<T> F = face_flux(face_plus<T, false>(wo, sx), face_minus<T, false>(wr1, sx1), gam, igm1);
+    const Flux<T> Fm = shr1(F);         // flux through face c-1/2
 
-    // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11)
-    T r0 = (F.f0 - Fm.f0) * a.idx + (G.f0 - Gp.f0) * a.idy;
-    T r1 = (F.f1 - Fm.f1) * a.idx + (G.f2 - Gp.f2) * a.idy;
-    T r2 = (F.f2 - Fm.f2) * a.idx + (G.f1 - Gp.f1) * a.idy;
-    T r3 = (F.f3 - Fm.f3) * a.idx + (G.f3 - Gp.f3) * a.idy;
+    // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11),
+    // formed as (dF + dG (dx/dy)) / dx: with square cells dx/dy = 1 and the
+    // single rounding of dF + dG keeps the x/y mirror symmetry exact.
+    const T r0 = fma(G.f0 - Gp.f0, a.kxy, F.f0 - Fm.f0) * a.idx;
+    const T r1 = fma(G.f2 - Gp.f2, a.kxy, F.f1 - Fm.f1) * a.idx;
+    const T r2 = fma(G.f1 - Gp.f1, a.kxy, F.f2 - Fm.f2) * a.idx;
+    const T r3 = fma(G.f3 - Gp.f3, a.kxy, F.f3 - Fm.f3) * a.idx;
 
-    T u0 = combine<MODE>(qo[0], b[0], r0, dt);
-    T u1 = combine<MODE>(qo[1], b[1], r1, dt);
-    T u2 = combine<MODE>(qo[2], b[2], r2, dt);
-    T u3 = combine<MODE>(qo[3], b[3], r3, dt);
-    if (out_lane) {
-      O0[off] = u0;
-      O1[off] = u1;
-      O2[off] = u2;
-      O3[off] = u3;
+    const int sl = o % 3;
+    const T u0 = combine<MODE>(my[sl][0][lane], bc[0], r0, dt);
+    const T u1 = combine<MODE>(my[sl][1][lane], bc[1], r1, dt);
+    const T u2 = combine<MODE>(my[sl][2][lane], bc[2], r2, dt);
+    const T u3 = combine<MODE>(my[sl][3][lane], bc[3], r3, dt);
+    if constexpr (MODE == kCorrector) {
+      if (o + 2 < y1) {
+        const int o2 = off + 2 * nx;
+        bc[0] = B0[o2];
+        bc[1] = B1[o2];
+        bc[2] = B2[o2];
+        bc[3] = B3[o2];
+      }
+    }
+    {
+      if (out_lane) {
+        const int k = w * kTileW + lane - kHalo;
+        obuf[par][0][k] = u0;
+        obuf[par][1][k] = u1;
+        obuf[par][2][k] = u2;
+        obuf[par][3][k] = u3;
+      }
+      __syncthreads();
+      const int col = xb + kst;
+      if (kst < BW && col < nx) {
+        const int so = o * nx + col;
+        O0[so] = obuf[par][0][kst];
+        O1[so] = obuf[par][1][kst];
+        O2[so] = obuf[par][2][kst];
+        O3[so] = obuf[par][3][kst];
+      }
+      par ^= 1;
     }
     if constexpr (MODE == kCorrector) {
       if (a.reduce) {
         // CFL wave speed of the new state, (|u|+c)/dx + (|v|+c)/dy
-        Prim<T> w = to_prim(u0, u1, u2, u3, gm1);
-        T cs = sqrt(gam * w.p / w.r);
-        T s = (fabs(w.u) + cs) * a.idx + (fabs(w.v) + cs) * a.idy;
-        bool ok = (w.r > T(0)) && (w.p > T(0)) && (s <= T(3.0e38));
+        const T ir = rcp(u0);
+        const T uu = u1 * ir, vv = u2 * ir;
+        const T pp = gm1 * (u3 - T(0.5) * (u1 * uu + u2 * vv));
+        const T c2 = gam * pp * ir;
+        const T cs = c2 * rsq(c2);
+        const T sp = (fabs(uu) + cs) * a.idx + (fabs(vv) + cs) * a.idy;
+        const bool ok = (u0 > T(0)) && (pp > T(0)) && (sp <= T(3.0e38));
         if (out_lane) {
-          if (ok) smax = fmax(smax, double(s));
+          if (ok) smax = fmax(smax, double(sp));
           else bad = true;
         }
       }
     }
+    wo = wn;  // slot of row o now holds row o+2
+  };
 
-    // slide the window one row up
-    Gp = G;
-    wo = wo1;
-    wo1 = wn;
-    s_o = s_o1;
-    d_o = dn;
-    for (int k = 0; k < 4; ++k) {
-      qo[k] = qo1[k];
-      qo1[k] = qn[k];
-      qn[k] = qnn[k];
-    }
+  for (int o = y0; o < y1; o += 2) {
+    row(o, QA, BA, W0, W1, Sg0, Sg1, Gf0, Gf1);
+    if (o + 1 < y1) row(o + 1, QB, BB, W1, W0, Sg1, Sg0, Gf1, Gf0);
   }
 
   if constexpr (MODE == kCorrector) {
@@ -240,10 +310,13 @@ __global__ __launch_bounds__(256) void wavespeed_kernel(const T* __restrict__ U,
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride) {
     T q0 = U[q], q1 = U[plane + q], q2 = U[2 * plane + q], q3 = U[3 * plane + q];
-    Prim<T> w = to_prim(q0, q1, q2, q3, gm1);
-    T cs = sqrt(gamma * w.p / w.r);
-    T s = (fabs(w.u) + cs) * idx + (fabs(w.v) + cs) * idy;
-    bool ok = (w.r > T(0)) && (w.p > T(0)) && (s <= T(3.0e38));
+    const T ir = rcp(q0);
+    const T uu = q1 * ir, vv = q2 * ir;
+    const T pp = gm1 * (q3 - T(0.5) * (q1 * uu + q2 * vv));
+    const T c2 = gamma * pp * ir;
+    const T cs = c2 * rsq(c2);
+    const T s = (fabs(uu) + cs) * idx + (fabs(vv) + cs) * idy;
+    const bool ok = (q0 > T(0)) && (pp > T(0)) && (s <= T(3.0e38));
     if (ok) smax = fmax(smax, double(s));
     else bad = true;
   }
@@ -385,6 +458,7 @@ static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base
   a.tiles_x = g.tiles_x;
   a.tiles_y = g.tiles_y;
   a.rows = g.rows_per_wave;
+  a.blocks_x = g.blocks_x;
   a.blocks = g.blocks;
   a.blocks_pad = g.blocks_pad;
   a.plane = (long long)g.nx * g.ny;
@@ -394,10 +468,12 @@ static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base
   a.beta = T(g.beta);
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
+  a.kxy = T(g.dx / g.dy);
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;
-  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY>), dim3(g.blocks_pad), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY>), dim3(g.blocks_pad), dim3(kWave * waves_per_block<T>()), 0,
+                     s, a);
   return hipGetLastError();
 }
 
@@ -506,8 +582,9 @@ Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, d
   if (r > ny) r = ny;
   g.rows_per_wave = r;
   g.tiles_y = (ny + r - 1) / r;
-  const long long waves = (long long)g.tiles_x * g.tiles_y;
-  g.blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  g.wpb = dtype == 0 ? waves_per_block<double>() : waves_per_block<float>();
+  g.blocks_x = (g.tiles_x + g.wpb - 1) / g.wpb;
+  g.blocks = g.blocks_x * g.tiles_y;
   g.blocks_pad = (g.blocks + kXcds - 1) / kXcds * kXcds;
   return g;
 }

@@ -18,6 +18,8 @@ struct Grid {
   int dtype;            // 0 = double, 1 = float
   int tiles_x, tiles_y; // wave tiles of kTileW columns x rows_per_wave rows
   int rows_per_wave;
+  int wpb;              // waves per stage block (a block is wpb adjacent tiles)
+  int blocks_x;         // blocks per row band: ceil(tiles_x / wpb)
   int blocks, blocks_pad;
 };
 

@@ -61,7 +61,7 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(dx=0.0), dict(dy=float("nan")),
-                                 dict(gamma=1.0), dict(gamma=3.5), dict(beta=-0.1), dict(beta=2.5),
+                                 dict(gamma=1.0), dict(gamma=3.5), dict(beta=-0.1), dict(beta=2.5), dict(beta=0.5),
                                  dict(cfl=0.0), dict(bc_x=2), dict(bc_y=-1), dict(dtype=7),
                                  dict(nx=65536, ny=65536)])
 def test_init_rejects(bad):
