@@ -215,11 +215,20 @@ def profile_pass(L, W, n):
         torch.cuda.synchronize()
         del U, S
         torch.cuda.empty_cache()
-    # plain copy kernel: 1 GiB read + 1 GiB written per launch
+    # plain copies of known size for the counter calibration: 1 GiB read +
+    # 1 GiB written per launch, by torch's copy kernel and by the runtime's
+    # device-to-device memcpy
+    import ctypes
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(5):
+    for _ in range(3):
         dst.copy_(src)
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(3):
+        rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), 1 << 30, 3, stream)
+        assert rc == 0, rc
     torch.cuda.synchronize()
     log("profile pass done")
 
