@@ -1,12 +1,16 @@
-"""Rounding floor of long shock-tube runs.
+"""Rounding floor of long runs.
 
 Perturbing the oracle's own state by random one-ulp noise after every step
 of the Sod run (400x4, CFL 0.5, t = 0.2, 555 steps) and comparing with the
 unperturbed run measures how far last-bit differences grow through the
 shock and the rarefaction fan.  This floor is what any implementation that
 does not reproduce the oracle bit for bit can reach, and it sets the
-parity bar of the full GPU Sod run (1e-11 relative L-infinity)."""
+parity bar of the full GPU Sod run (1e-11 relative L-infinity).  The same
+holds for the smooth isentropic vortex once a run is long: at 512^2 (1105
+steps to t = 2) the floor reaches ~5e-12, while at 256^2 (553 steps) it
+stays below 1e-12, where the GPU runs keep the 1e-12 bar."""
 import numpy as np
+import pytest
 
 import oracle
 import workloads
@@ -38,3 +42,31 @@ def test_sod_rounding_floor(oracle_lib):
     # in L1 the same noise stays tiny
     l1 = np.abs(B - A).sum(axis=(1, 2)) / np.abs(A).sum(axis=(1, 2)).clip(min=1e-300)
     assert np.all(l1[[0, 1, 3]] < 3e-13), l1
+
+
+def _vortex_floor(oracle_lib, n):
+    U, cfg = workloads.vortex(n)
+    P = params_from(cfg)
+    rng = np.random.default_rng(0)
+    A, B, t, peak = U.copy(), U.copy(), 0.0, np.zeros(4)
+    while t < cfg["t_end"]:
+        rc, dt = oracle_lib.dt(P, A)
+        last = dt >= cfg["t_end"] - t
+        dt = cfg["t_end"] - t if last else dt
+        A = oracle_lib.step(P, A, dt)
+        B = oracle_lib.step(P, B, dt)
+        B = B + np.spacing(B) * rng.choice([-1.0, 0.0, 1.0], size=B.shape)
+        t = cfg["t_end"] if last else t + dt
+        peak = np.maximum(peak, _rel_linf(B, A))
+    return peak
+
+
+def test_vortex_rounding_floor_256(oracle_lib):
+    peak = _vortex_floor(oracle_lib, 256)
+    assert np.all(peak < 1e-12), peak
+
+
+@pytest.mark.slow
+def test_vortex_rounding_floor_512(oracle_lib):
+    peak = _vortex_floor(oracle_lib, 512)
+    assert peak[0] > 1e-12 and np.all(peak < 1e-11), peak
