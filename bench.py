@@ -254,7 +254,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the Lagrange-flux path is built and measured on a single "
-              "MI355X (multi-GPU domain decomposition is a design, not part of this build); "
+              "MI355X (the multi-GPU domain decomposition is designed but not implemented); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

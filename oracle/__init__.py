@@ -1,7 +1,7 @@
 """Plain FP64 CPU oracle of the second-order Lagrange-flux scheme.
 
-TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
-the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check of the entry
+module and the CPU-baseline leg of ``bench.py`` may import this package.  The
 product path (``paper_1607_08710_amd``) never imports it, and the two share
 no code: the oracle is the C file ``lfo.c`` next to this module, loaded
 here through ctypes.

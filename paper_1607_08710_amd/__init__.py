@@ -58,7 +58,7 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it first "
-                              "(python -c 'import __graft_entry__ as g; g.build()')")
+                              "(python -m paper_1607_08710_amd._build)")
         L = ctypes.CDLL(LIB_PATH)
         vp, d, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64
         L.lf_init.argtypes = [ctypes.POINTER(lf_params), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]

@@ -121,3 +121,17 @@ def test_advance_clamps_to_t_end(oracle_lib):
     assert rc == 0 and t == 0.05
     assert np.all(dts[:-1] > 0) and dts[-1] <= dts[-2] * 1.5
     assert abs(dts.sum() - 0.05) < 1e-15
+
+
+def test_totals_against_exact_sum(oracle_lib):
+    """lfo_totals is a compensated sum times dx*dy: against math.fsum (the
+    correctly rounded sum) it agrees to one rounding of the product, also
+    on data built to cancel."""
+    import math
+    rng = np.random.default_rng(12)
+    U = rng.standard_normal((4, 37, 53)) * 10.0 ** rng.integers(-8, 8, size=(4, 37, 53))
+    P = _P(53, 37, d=0.25)
+    got = oracle_lib.totals(P, U)
+    for f in range(4):
+        exact = math.fsum(U[f].ravel()) * 0.25 * 0.25
+        assert got[f] == pytest.approx(exact, rel=4e-16, abs=1e-300)
