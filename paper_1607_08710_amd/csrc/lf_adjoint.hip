@@ -1,201 +1,311 @@
 // lf_adjoint.hip -- transpose of the residual's Jacobian, v = J_R(U)^T g,
 // in gather form (no atomics), and the two adjoint stages of the Heun step.
 //
-// R_i = (F_{i+1/2} - F_{i-1/2})/dx + (G_{j+1/2} - G_{j-1/2})/dy, and the
-// flux through x-face k (between cells k-1 and k) depends on the
-// primitive states of cells k-2 .. k+1 (MUSCL slopes of k-1 and k).  Cell
-// i therefore receives contributions from x-faces k = i-1 .. i+2 and the
-// same four y-faces; each face's cotangent is (g_{k-1} - g_k)/dx.  A
-// thread owns one cell, recomputes the forward state of each of its eight
-// faces and pulls the face cotangent back through eq. (12), eqs. (13)-(14)
-// and the limited reconstruction (eq. (sweby)) onto its own primitive
-// variables, then through the perfect-gas law onto its conservative ones.
+// R_i = (F_{i+1/2} - F_{i-1/2})/dx + (G_{j+1/2} - G_{j-1/2})/dy, and the flux
+// through x-face k (between cells k-1 and k) depends on the primitive
+// states of cells k-2 .. k+1 (MUSCL slopes of k-1 and k).  The face's
+// cotangent is (g_{k-1} - g_k)/dx; pulled back through eq. (12), eqs.
+// (13)-(14) and the limited reconstruction (eq. (sweby)) it yields four
+// "slot" contributions, to the primitive variables of cells k-2 .. k+1.
+// A cell collects the slots of x-faces k = i-1 .. i+2 and of the same four
+// y-faces, then its primitive cotangent goes through the perfect-gas law
+// onto its conservative variables.
 //
-// With transmissive boundaries the ghost cells copy the edge cell, so an
-// edge cell also collects the contributions of the stencil slots that
-// point at its ghosts; with periodic boundaries each (face, slot) pair is
-// visited exactly once through the extended face index.
+// Kernel layout (same idea as the forward stage kernel).  A wave owns 64
+// consecutive columns and produces the middle 56 (the adjoint stencil
+// reaches three cells to each side); it marches up a strip of rows.  Every
+// face is evaluated once per wave: x-faces across the lanes, with the slot
+// contributions moved to their cells by DPP shifts; y-faces one per row,
+// with the slot contributions accumulated in a four-row register window.
+// A row is finished when its last y-face (two rows above it) has been
+// processed.  Results go through LDS and are stored as whole 128-byte lines.
+//
+// Boundaries.  Transmissive: ghost cells copy the edge cell, so the slots
+// that point at ghost cells are folded onto the edge cell; faces beyond the
+// boundary do not exist (their cotangent is zero: g is zero outside).
+// Periodic: the stencil data wrap, faces are indexed in unwrapped
+// coordinates and each (cell, face) pair is visited exactly once.
 #include "lf_internal.h"
 
 namespace lf {
 
+constexpr int kAdjHalo = 4;
+constexpr int kAdjTileW = kWave - 2 * kAdjHalo;  // 56 output columns per wave
+
 template <typename T>
 struct AdjArgs {
-  const T* U;
-  const T* g;
-  const T* lam;
+  const T* U;    // state at which J_R is taken
+  const T* g;    // cotangent of R
+  const T* lam;  // lambda^{n+1} (mode kAdjPred)
   T* out;
   int nx, ny;
+  int rows;      // strip height
+  int blocks_x, blocks, blocks_pad;
   long long plane;
   T gamma, gm1, inv_gm1, beta, idx, idy;
   double dt;
 };
 
 template <typename T>
-struct Slots {
-  FaceState<T> s[4];
+struct P4 {
+  T r, u, v, p;
 };
 
-// Forward face state of one stencil and the cotangents of its four cells.
 template <typename T>
-__device__ __forceinline__ void face_backprop(const FaceState<T> (&W)[4], const Flux<T>& fb, T gamma,
-                                              T inv_gm1, T beta, Slots<T>& out) {
-  T pa1[4], pb1[4], pa2[4], pb2[4];
-  T wl[4], wr[4];
-  const T* w0 = &W[0].r;
-  const T* w1 = &W[1].r;
-  const T* w2 = &W[2].r;
-  const T* w3 = &W[3].r;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    T a1 = w1[v] - w0[v], b1 = w2[v] - w1[v];
-    T a2 = w2[v] - w1[v], b2 = w3[v] - w2[v];
-    T s1 = sweby(a1, b1, beta), s2 = sweby(a2, b2, beta);
-    sweby_d(a1, b1, beta, pa1[v], pb1[v]);
-    sweby_d(a2, b2, beta, pa2[v], pb2[v]);
-    wl[v] = fma(T(0.5), s1, w1[v]);
-    wr[v] = fma(T(-0.5), s2, w2[v]);
-  }
-  FaceState<T> L = {wl[0], wl[1], wl[2], wl[3]};
-  FaceState<T> R = {wr[0], wr[1], wr[2], wr[3]};
-  FaceState<T> Lb, Rb;
-  face_flux_vjp(L, R, gamma, inv_gm1, fb, Lb, Rb);
-  const T* lb = &Lb.r;
-  const T* rb = &Rb.r;
-  T* o0 = &out.s[0].r;
-  T* o1 = &out.s[1].r;
-  T* o2 = &out.s[2].r;
-  T* o3 = &out.s[3].r;
+__device__ __forceinline__ P4<T> p4_shl(const P4<T>& a) {
+  return {shl1(a.r), shl1(a.u), shl1(a.v), shl1(a.p)};
+}
+template <typename T>
+__device__ __forceinline__ P4<T> p4_shr(const P4<T>& a) {
+  return {shr1(a.r), shr1(a.u), shr1(a.v), shr1(a.p)};
+}
+template <typename T>
+__device__ __forceinline__ P4<T> p4_add(const P4<T>& a, const P4<T>& b) {
+  return {a.r + b.r, a.u + b.u, a.v + b.v, a.p + b.p};
+}
+template <typename T>
+__device__ __forceinline__ P4<T> p4_sel(bool c, const P4<T>& a) {
+  return {c ? a.r : T(0), c ? a.u : T(0), c ? a.v : T(0), c ? a.p : T(0)};
+}
+
+// Slope, its two partial derivatives and the two face values of one cell
+// for one variable: wm = w - sigma/2 (its lower face), wp = w + sigma/2.
+template <typename T>
+struct SlopeD {
+  P4<T> s, da, db;
+};
+
+template <typename T>
+__device__ __forceinline__ SlopeD<T> slope_d(const P4<T>& dm, const P4<T>& dp, T beta) {
+  SlopeD<T> o;
+  o.s = {sweby(dm.r, dp.r, beta), sweby(dm.u, dp.u, beta), sweby(dm.v, dp.v, beta), sweby(dm.p, dp.p, beta)};
+  sweby_d(dm.r, dp.r, beta, o.da.r, o.db.r);
+  sweby_d(dm.u, dp.u, beta, o.da.u, o.db.u);
+  sweby_d(dm.v, dp.v, beta, o.da.v, o.db.v);
+  sweby_d(dm.p, dp.p, beta, o.da.p, o.db.p);
+  return o;
+}
+
+// One face: left cell state w1 with slope data S1 (cell k-1), right cell
+// w2 with S2 (cell k); fb the flux cotangent in the face frame.  Returns
+// the four slot contributions in (rho, u, v, p) order.  YF selects the
+// y-face frame (normal velocity v).
+template <typename T, bool YF>
+__device__ __forceinline__ void face_slots(const P4<T>& w1, const SlopeD<T>& S1, const P4<T>& w2,
+                                           const SlopeD<T>& S2, const Flux<T>& fb, T gamma, T inv_gm1,
+                                           P4<T>& s0, P4<T>& s1, P4<T>& s2, P4<T>& s3) {
   const T h = T(0.5);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    o0[v] = -h * pa1[v] * lb[v];
-    o1[v] = (T(1) + h * (pa1[v] - pb1[v])) * lb[v] + h * pa2[v] * rb[v];
-    o2[v] = h * pb1[v] * lb[v] + (T(1) - h * (pa2[v] - pb2[v])) * rb[v];
-    o3[v] = -h * pb2[v] * rb[v];
+  const P4<T> L = {fma(h, S1.s.r, w1.r), fma(h, S1.s.u, w1.u), fma(h, S1.s.v, w1.v), fma(h, S1.s.p, w1.p)};
+  const P4<T> R = {fma(-h, S2.s.r, w2.r), fma(-h, S2.s.u, w2.u), fma(-h, S2.s.v, w2.v), fma(-h, S2.s.p, w2.p)};
+  FaceState<T> FL, FR, Lb, Rb;
+  if constexpr (YF) {
+    FL = {L.r, L.v, L.u, L.p};
+    FR = {R.r, R.v, R.u, R.p};
+  } else {
+    FL = {L.r, L.u, L.v, L.p};
+    FR = {R.r, R.u, R.v, R.p};
   }
+  face_flux_vjp(FL, FR, gamma, inv_gm1, fb, Lb, Rb);
+  P4<T> lb, rb;
+  if constexpr (YF) {
+    lb = {Lb.r, Lb.ut, Lb.un, Lb.p};
+    rb = {Rb.r, Rb.ut, Rb.un, Rb.p};
+  } else {
+    lb = {Lb.r, Lb.un, Lb.ut, Lb.p};
+    rb = {Rb.r, Rb.un, Rb.ut, Rb.p};
+  }
+  // w^L = w1 + phi(w1 - w0, w2 - w1)/2,  w^R = w2 - phi(w2 - w1, w3 - w2)/2
+  auto one = [&](T l, T r, T a1, T b1, T a2, T b2, T& o0, T& o1, T& o2, T& o3) {
+    o0 = -h * a1 * l;
+    o1 = fma(h * (a1 - b1), l, l) + h * a2 * r;
+    o2 = h * b1 * l + fma(-h * (a2 - b2), r, r);
+    o3 = -h * b2 * r;
+  };
+  one(lb.r, rb.r, S1.da.r, S1.db.r, S2.da.r, S2.db.r, s0.r, s1.r, s2.r, s3.r);
+  one(lb.u, rb.u, S1.da.u, S1.db.u, S2.da.u, S2.db.u, s0.u, s1.u, s2.u, s3.u);
+  one(lb.v, rb.v, S1.da.v, S1.db.v, S2.da.v, S2.db.v, s0.v, s1.v, s2.v, s3.v);
+  one(lb.p, rb.p, S1.da.p, S1.db.p, S2.da.p, S2.db.p, s0.p, s1.p, s2.p, s3.p);
 }
 
 template <typename T>
-__device__ __forceinline__ Prim<T> load_prim(const AdjArgs<T>& a, int off) {
-  return to_prim(a.U[off], a.U[a.plane + off], a.U[2 * a.plane + off], a.U[3 * a.plane + off], a.gm1);
+__device__ __forceinline__ P4<T> prim4(T q0, T q1, T q2, T q3, T gm1) {
+  Prim<T> w = to_prim(q0, q1, q2, q3, gm1);
+  return {w.r, w.u, w.v, w.p};
 }
 
 template <typename T, int MODE, int BCX, int BCY>
-__global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs<T> a) {
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.plane) return;
+__global__ __launch_bounds__(kWave * waves_per_block<T>()) void adjoint_kernel(AdjArgs<T> a) {
+  constexpr int WPB = waves_per_block<T>();
+  constexpr bool XT = BCX == kBcTransmissive;
+  constexpr bool YT = BCY == kBcTransmissive;
+  const int lb_ = xcd_block(blockIdx.x, a.blocks_pad);
+  if (lb_ >= a.blocks) return;  // whole block
+  const int by = lb_ / a.blocks_x;
+  const int bx = lb_ - by * a.blocks_x;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1);
   const int nx = a.nx, ny = a.ny;
-  const int j = (int)(q / nx);
-  const int i = (int)(q - (long long)j * nx);
+  const int c = (bx * WPB + w) * kAdjTileW - kAdjHalo + lane;  // unwrapped column of this lane
+  const int cm = map_index<BCX>(c, nx);
+  const bool c_in = c >= 0 && c < nx;
+  const bool out_lane = lane >= kAdjHalo && lane < kWave - kAdjHalo && c < nx;
+  // x-face computed by this lane: k = c + 1, between columns c and c + 1
+  const bool xface = !XT || (c >= -1 && c <= nx - 1);
+  const int y0 = by * a.rows;
+  const int y1 = min(y0 + a.rows, ny);
   const long long P = a.plane;
-  T wr = 0, wu = 0, wv = 0, wp = 0;  // cotangent of (rho, u, v, p) of cell (i, j)
+  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta;
 
-  // ---- x-faces k = i-1 .. i+2 (face k between cells k-1 and k) ----
+  auto load_u = [&](int row) -> P4<T> {
+    const int o = map_index<BCY>(row, ny) * nx + cm;
+    return prim4(a.U[o], a.U[P + o], a.U[2 * P + o], a.U[3 * P + o], gm1);
+  };
+  // cotangent of R at (row, this lane's column): zero outside a
+  // transmissive domain (those cells do not exist)
+  auto load_g = [&](int row) -> P4<T> {
+    const bool in = (!YT || (row >= 0 && row < ny)) && (!XT || c_in);
+    const int o = map_index<BCY>(row, ny) * nx + cm;
+    P4<T> g = {a.g[o], a.g[P + o], a.g[2 * P + o], a.g[3 * P + o]};
+    return p4_sel(in, g);
+  };
+
+  constexpr int BW = WPB * kAdjTileW;
+  __shared__ T obuf[2][4][BW];
+  const int xb = bx * BW;
+  const int kst = w * kWave + lane;
+  int par = 0;
+
+  // window: prim rows k-2 .. k+1, g rows k-2 .. k, y-accumulators rows
+  // k-2 .. k+1 (slots rotate every row); slope data of row k-1.
+  P4<T> Wm2 = load_u(y0 - 3), Wm1 = load_u(y0 - 2), W0 = load_u(y0 - 1);
+  P4<T> Gm2 = {T(0), T(0), T(0), T(0)}, Gm1 = load_g(y0 - 2);
+  const P4<T> Z = {T(0), T(0), T(0), T(0)};
+  P4<T> Am2 = Z, Am1 = Z, A0 = Z;  // accumulators for rows k-2, k-1, k
+  P4<T> ghost_lo = Z;              // transmissive: slots aimed at rows < 0
+  // slope of row k-1 for the first face (k = y0 - 1): rows y0-3, y0-2, y0-1
+  // (Wm2, Wm1, W0 hold rows k-2, k-1, k for k = y0 - 1)
+  SlopeD<T> Sk1 = slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
+                          {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta);
+
 #pragma unroll 1
-  for (int kk = -1; kk <= 2; ++kk) {
-    const int k = i + kk;
-    if (BCX == kBcTransmissive && (k < 0 || k > nx)) continue;
-    T gl[4] = {0, 0, 0, 0}, gr[4] = {0, 0, 0, 0};
-    const bool has_l = (BCX == kBcPeriodic) || (k - 1 >= 0);
-    const bool has_r = (BCX == kBcPeriodic) || (k < nx);
-    if (has_l) {
-      const int o = j * nx + map_index<BCX>(k - 1, nx);
-      for (int f = 0; f < 4; ++f) gl[f] = a.g[f * P + o];
+  for (int k = y0 - 1; k <= y1 + 1; ++k) {
+    // new data: prim row k+1, g row k
+    const P4<T> W1 = load_u(k + 1);
+    const P4<T> Gk = load_g(k);
+    // slope of row k (rows k-1, k, k+1)
+    const SlopeD<T> Sk = slope_d({W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p},
+                                 {W1.r - W0.r, W1.u - W0.u, W1.v - W0.v, W1.p - W0.p}, beta);
+    P4<T> A1 = Z;  // accumulator of row k+1 starts here
+    // ---- y-face k (between rows k-1 and k) ----
+    if (!YT || (k >= 0 && k <= ny)) {
+      const Flux<T> fb = {(Gm1.r - Gk.r) * a.idy, (Gm1.v - Gk.v) * a.idy, (Gm1.u - Gk.u) * a.idy,
+                          (Gm1.p - Gk.p) * a.idy};
+      P4<T> s0, s1, s2, s3;
+      face_slots<T, true>(Wm1, Sk1, W0, Sk, fb, gam, igm1, s0, s1, s2, s3);
+      Am2 = p4_add(Am2, s0);
+      Am1 = p4_add(Am1, s1);
+      A0 = p4_add(A0, s2);
+      A1 = s3;
     }
-    if (has_r) {
-      const int o = j * nx + map_index<BCX>(k, nx);
-      for (int f = 0; f < 4; ++f) gr[f] = a.g[f * P + o];
+    // ---- row r = k-2 is complete in y ----
+    const int r = k - 2;
+    if constexpr (YT) {
+      if (r < 0) ghost_lo = p4_add(ghost_lo, Am2);
     }
-    Flux<T> fb = {(gl[0] - gr[0]) * a.idx, (gl[1] - gr[1]) * a.idx, (gl[2] - gr[2]) * a.idx,
-                  (gl[3] - gr[3]) * a.idx};
-    FaceState<T> W[4];
-    int cell[4];
-    for (int s = 0; s < 4; ++s) {
-      cell[s] = map_index<BCX>(k - 2 + s, nx);
-      Prim<T> w = load_prim(a, j * nx + cell[s]);
-      W[s] = {w.r, w.u, w.v, w.p};
-    }
-    Slots<T> sl;
-    face_backprop(W, fb, a.gamma, a.inv_gm1, a.beta, sl);
-    for (int s = 0; s < 4; ++s) {
-      const bool mine = (BCX == kBcPeriodic) ? (s == 2 - kk) : (cell[s] == i);
-      if (mine) {
-        wr += sl.s[s].r;
-        wu += sl.s[s].un;
-        wv += sl.s[s].ut;
-        wp += sl.s[s].p;
+    if (r >= y0) {
+      P4<T> tot = Am2;
+      if constexpr (YT) {
+        if (r == 0) tot = p4_add(tot, ghost_lo);
+        if (r == ny - 1) tot = p4_add(tot, p4_add(Am1, A0));  // rows ny, ny+1 are ghosts
       }
-    }
-  }
-
-  // ---- y-faces k = j-1 .. j+2 (frame: normal velocity v) ----
-#pragma unroll 1
-  for (int kk = -1; kk <= 2; ++kk) {
-    const int k = j + kk;
-    if (BCY == kBcTransmissive && (k < 0 || k > ny)) continue;
-    T gl[4] = {0, 0, 0, 0}, gr[4] = {0, 0, 0, 0};
-    const bool has_l = (BCY == kBcPeriodic) || (k - 1 >= 0);
-    const bool has_r = (BCY == kBcPeriodic) || (k < ny);
-    if (has_l) {
-      const int o = map_index<BCY>(k - 1, ny) * nx + i;
-      for (int f = 0; f < 4; ++f) gl[f] = a.g[f * P + o];
-    }
-    if (has_r) {
-      const int o = map_index<BCY>(k, ny) * nx + i;
-      for (int f = 0; f < 4; ++f) gr[f] = a.g[f * P + o];
-    }
-    // flux frame: (mass, y-momentum, x-momentum, energy)
-    Flux<T> fb = {(gl[0] - gr[0]) * a.idy, (gl[2] - gr[2]) * a.idy, (gl[1] - gr[1]) * a.idy,
-                  (gl[3] - gr[3]) * a.idy};
-    FaceState<T> W[4];
-    int cell[4];
-    for (int s = 0; s < 4; ++s) {
-      cell[s] = map_index<BCY>(k - 2 + s, ny);
-      Prim<T> w = load_prim(a, cell[s] * nx + i);
-      W[s] = {w.r, w.v, w.u, w.p};
-    }
-    Slots<T> sl;
-    face_backprop(W, fb, a.gamma, a.inv_gm1, a.beta, sl);
-    for (int s = 0; s < 4; ++s) {
-      const bool mine = (BCY == kBcPeriodic) ? (s == 2 - kk) : (cell[s] == j);
-      if (mine) {
-        wr += sl.s[s].r;
-        wv += sl.s[s].un;
-        wu += sl.s[s].ut;
-        wp += sl.s[s].p;
+      // x-faces of row r across the lanes (Wm2 = prim row r, Gm2 = g row r)
+      const P4<T> wr1 = p4_shl(Wm2);
+      const P4<T> dxp = {wr1.r - Wm2.r, wr1.u - Wm2.u, wr1.v - Wm2.v, wr1.p - Wm2.p};
+      const P4<T> dxm = p4_shr(dxp);
+      const SlopeD<T> Sx = slope_d(dxm, dxp, beta);
+      SlopeD<T> Sx1;
+      Sx1.s = p4_shl(Sx.s);
+      Sx1.da = p4_shl(Sx.da);
+      Sx1.db = p4_shl(Sx.db);
+      const P4<T> g1 = p4_shl(Gm2);
+      const Flux<T> fb = {(Gm2.r - g1.r) * a.idx, (Gm2.u - g1.u) * a.idx, (Gm2.v - g1.v) * a.idx,
+                          (Gm2.p - g1.p) * a.idx};
+      P4<T> s0, s1, s2, s3;
+      face_slots<T, false>(Wm2, Sx, wr1, Sx1, fb, gam, igm1, s0, s1, s2, s3);
+      // a face that does not exist contributes nothing (select, not
+      // multiply: halo lanes may hold non-finite intermediates)
+      s0 = p4_sel(xface, s0);
+      s1 = p4_sel(xface, s1);
+      s2 = p4_sel(xface, s2);
+      s3 = p4_sel(xface, s3);
+      // lane c collects slot 0 of the face at lane c+1, slot 1 of its own,
+      // slot 2 of lane c-1 and slot 3 of lane c-2
+      P4<T> tx = p4_add(p4_add(p4_shl(s0), s1), p4_add(p4_shr(s2), p4_shr(p4_shr(s3))));
+      if constexpr (XT) {
+        // ghost columns -1, -2 fold onto column 0; nx, nx+1 onto nx-1
+        const P4<T> l1 = p4_shr(tx), l2 = p4_shr(l1);
+        const P4<T> r1 = p4_shl(tx), r2 = p4_shl(r1);
+        if (c == 0) tx = p4_add(tx, p4_add(l1, l2));
+        if (c == nx - 1) tx = p4_add(tx, p4_add(r1, r2));
       }
+      tot = p4_add(tot, tx);
+      // primitive -> conservative: v = (dw/dU)^T wbar
+      const T ir = rcp(Wm2.r);
+      const T u = Wm2.u, v = Wm2.v;
+      T vv[4];
+      vv[0] = tot.r - (u * tot.u + v * tot.v) * ir + gm1 * T(0.5) * (u * u + v * v) * tot.p;
+      vv[1] = tot.u * ir - gm1 * u * tot.p;
+      vv[2] = tot.v * ir - gm1 * v * tot.p;
+      vv[3] = gm1 * tot.p;
+      const T gg[4] = {Gm2.r, Gm2.u, Gm2.v, Gm2.p};
+      T res[4];
+      const int off = r * nx + cm;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if constexpr (MODE == kVjp) {
+          res[f] = vv[f];
+        } else if constexpr (MODE == kAdjCorr) {
+          res[f] = T(0.5 * (double(gg[f]) - a.dt * double(vv[f])));  // mu = (lam - dt v)/2
+        } else {
+          const T lam = out_lane ? a.lam[f * P + off] : T(0);  // lam/2 + mu - dt v
+          res[f] = T(0.5 * double(lam) + double(gg[f]) - a.dt * double(vv[f]));
+        }
+      }
+      if (out_lane) {
+        const int kk = w * kAdjTileW + lane - kAdjHalo;
+        obuf[par][0][kk] = res[0];
+        obuf[par][1][kk] = res[1];
+        obuf[par][2][kk] = res[2];
+        obuf[par][3][kk] = res[3];
+      }
+      __syncthreads();
+      const int col = xb + kst;
+      if (kst < BW && col < nx) {
+        const int so = r * nx + col;
+        a.out[so] = obuf[par][0][kst];
+        a.out[P + so] = obuf[par][1][kst];
+        a.out[2 * P + so] = obuf[par][2][kst];
+        a.out[3 * P + so] = obuf[par][3][kst];
+      }
+      par ^= 1;
     }
-  }
-
-  // ---- primitive -> conservative: v = (dw/dU)^T wbar ----
-  const T q0 = a.U[q], q1 = a.U[P + q], q2 = a.U[2 * P + q];
-  const T ir = T(1) / q0;
-  const T u = q1 * ir, v = q2 * ir;
-  const T gm1 = a.gm1;
-  T v0 = wr - (u * wu + v * wv) * ir + gm1 * T(0.5) * (u * u + v * v) * wp;
-  T v1 = wu * ir - gm1 * u * wp;
-  T v2 = wv * ir - gm1 * v * wp;
-  T v3 = gm1 * wp;
-  T vv[4] = {v0, v1, v2, v3};
-  for (int f = 0; f < 4; ++f) {
-    T res;
-    if constexpr (MODE == kVjp) {
-      res = vv[f];
-    } else if constexpr (MODE == kAdjCorr) {
-      // mu = (lam - dt v) / 2 with g = lam
-      res = T(0.5 * (double(a.g[f * P + q]) - a.dt * double(vv[f])));
-    } else {
-      // lam^n = lam / 2 + mu - dt v with g = mu
-      res = T(0.5 * double(a.lam[f * P + q]) + double(a.g[f * P + q]) - a.dt * double(vv[f]));
-    }
-    a.out[f * P + q] = res;
+    // slide the window
+    Wm2 = Wm1;
+    Wm1 = W0;
+    W0 = W1;
+    Gm2 = Gm1;
+    Gm1 = Gk;
+    Am2 = Am1;
+    Am1 = A0;
+    A0 = A1;
+    Sk1 = Sk;
   }
 }
 
 template <typename T, int MODE, int BCX, int BCY>
 static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, const void* lam, void* out,
                                double dt, hipStream_t s) {
+  constexpr int WPB = waves_per_block<T>();
   AdjArgs<T> a;
   a.U = static_cast<const T*>(U);
   a.g = static_cast<const T*>(gv);
@@ -211,8 +321,17 @@ static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, con
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.dt = dt;
-  const long long nb = (a.plane + 255) / 256;
-  hipLaunchKernelGGL((adjoint_kernel<T, MODE, BCX, BCY>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  // strip height: 32 rows, halved (to 8) until ~8k waves exist
+  const int tiles_x = (g.nx + kAdjTileW - 1) / kAdjTileW;
+  int r = 32;
+  while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < 8192) r /= 2;
+  if (r > g.ny) r = g.ny;
+  a.rows = r;
+  const int tiles_y = (g.ny + r - 1) / r;
+  a.blocks_x = (tiles_x + WPB - 1) / WPB;
+  a.blocks = a.blocks_x * tiles_y;
+  a.blocks_pad = (a.blocks + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL((adjoint_kernel<T, MODE, BCX, BCY>), dim3(a.blocks_pad), dim3(kWave * WPB), 0, s, a);
   return hipGetLastError();
 }
 
