@@ -68,8 +68,8 @@ __device__ __forceinline__ P4<T> p4_sel(bool c, const P4<T>& a) {
   return {c ? a.r : T(0), c ? a.u : T(0), c ? a.v : T(0), c ? a.p : T(0)};
 }
 
-// Slope, its two partial derivatives and the two face values of one cell
-// for one variable: wm = w - sigma/2 (its lower face), wp = w + sigma/2.
+// Slope of one cell and its partial derivatives w.r.t. the backward and
+// forward differences, for the four primitive variables.
 template <typename T>
 struct SlopeD {
   P4<T> s, da, db;
@@ -78,11 +78,10 @@ struct SlopeD {
 template <typename T>
 __device__ __forceinline__ SlopeD<T> slope_d(const P4<T>& dm, const P4<T>& dp, T beta) {
   SlopeD<T> o;
-  o.s = {sweby(dm.r, dp.r, beta), sweby(dm.u, dp.u, beta), sweby(dm.v, dp.v, beta), sweby(dm.p, dp.p, beta)};
-  sweby_d(dm.r, dp.r, beta, o.da.r, o.db.r);
-  sweby_d(dm.u, dp.u, beta, o.da.u, o.db.u);
-  sweby_d(dm.v, dp.v, beta, o.da.v, o.db.v);
-  sweby_d(dm.p, dp.p, beta, o.da.p, o.db.p);
+  sweby_all(dm.r, dp.r, beta, o.s.r, o.da.r, o.db.r);
+  sweby_all(dm.u, dp.u, beta, o.s.u, o.da.u, o.db.u);
+  sweby_all(dm.v, dp.v, beta, o.s.v, o.da.v, o.db.v);
+  sweby_all(dm.p, dp.p, beta, o.s.p, o.da.p, o.db.p);
   return o;
 }
 
@@ -133,8 +132,11 @@ __device__ __forceinline__ P4<T> prim4(T q0, T q1, T q2, T q3, T gm1) {
   return {w.r, w.u, w.v, w.p};
 }
 
+// At least two waves per SIMD: without the bound the FP64 variants spill
+// past 256 registers into AGPRs and drop to one wave.
 template <typename T, int MODE, int BCX, int BCY>
-__global__ __launch_bounds__(kWave * waves_per_block<T>()) void adjoint_kernel(AdjArgs<T> a) {
+__global__ __launch_bounds__(kWave * waves_per_block<T>(), 8 / waves_per_block<T>())
+void adjoint_kernel(AdjArgs<T> a) {
   constexpr int WPB = waves_per_block<T>();
   constexpr bool XT = BCX == kBcTransmissive;
   constexpr bool YT = BCY == kBcTransmissive;
@@ -175,24 +177,24 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void adjoint_kernel(A
   const int kst = w * kWave + lane;
   int par = 0;
 
-  // window: prim rows k-2 .. k+1, g rows k-2 .. k, y-accumulators rows
-  // k-2 .. k+1 (slots rotate every row); slope data of row k-1.
+  // window: prim rows k-2 .. k+1, g row k-1, y-accumulators rows k-2 ..
+  // k+1 (slots rotate every row).  The slope data of row k-1 are
+  // recomputed rather than carried, and g of the finished row is read
+  // again (from cache): both keep the FP64 register footprint down.
   P4<T> Wm2 = load_u(y0 - 3), Wm1 = load_u(y0 - 2), W0 = load_u(y0 - 1);
-  P4<T> Gm2 = {T(0), T(0), T(0), T(0)}, Gm1 = load_g(y0 - 2);
+  P4<T> Gm1 = load_g(y0 - 2);
   const P4<T> Z = {T(0), T(0), T(0), T(0)};
   P4<T> Am2 = Z, Am1 = Z, A0 = Z;  // accumulators for rows k-2, k-1, k
   P4<T> ghost_lo = Z;              // transmissive: slots aimed at rows < 0
-  // slope of row k-1 for the first face (k = y0 - 1): rows y0-3, y0-2, y0-1
-  // (Wm2, Wm1, W0 hold rows k-2, k-1, k for k = y0 - 1)
-  SlopeD<T> Sk1 = slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
-                          {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta);
 
 #pragma unroll 1
   for (int k = y0 - 1; k <= y1 + 1; ++k) {
     // new data: prim row k+1, g row k
     const P4<T> W1 = load_u(k + 1);
     const P4<T> Gk = load_g(k);
-    // slope of row k (rows k-1, k, k+1)
+    // slopes of rows k-1 (rows k-2, k-1, k) and k (rows k-1, k, k+1)
+    const SlopeD<T> Sk1 = slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
+                                  {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta);
     const SlopeD<T> Sk = slope_d({W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p},
                                  {W1.r - W0.r, W1.u - W0.u, W1.v - W0.v, W1.p - W0.p}, beta);
     P4<T> A1 = Z;  // accumulator of row k+1 starts here
@@ -218,7 +220,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void adjoint_kernel(A
         if (r == 0) tot = p4_add(tot, ghost_lo);
         if (r == ny - 1) tot = p4_add(tot, p4_add(Am1, A0));  // rows ny, ny+1 are ghosts
       }
-      // x-faces of row r across the lanes (Wm2 = prim row r, Gm2 = g row r)
+      // x-faces of row r across the lanes (Wm2 = prim row r)
+      const P4<T> Gm2 = load_g(r);
       const P4<T> wr1 = p4_shl(Wm2);
       const P4<T> dxp = {wr1.r - Wm2.r, wr1.u - Wm2.u, wr1.v - Wm2.v, wr1.p - Wm2.p};
       const P4<T> dxm = p4_shr(dxp);
@@ -293,12 +296,10 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void adjoint_kernel(A
     Wm2 = Wm1;
     Wm1 = W0;
     W0 = W1;
-    Gm2 = Gm1;
     Gm1 = Gk;
     Am2 = Am1;
     Am1 = A0;
     A0 = A1;
-    Sk1 = Sk;
   }
 }
 

@@ -147,24 +147,26 @@ __device__ __forceinline__ T sweby(T a, T b, T beta) {
   return copysign(fmax(m, T(0)), a);
 }
 
-// Partial derivatives of sweby(a, b) with the conventions: zero when
-// ab <= 0; min(x, y) follows x when x <= y; max(m1, m2) follows m1 when
-// m1 >= m2.  (a and b share their sign when ab > 0, so the sign factors
-// cancel.)
+// Value and partial derivatives of eq. (sweby) in one pass, with the
+// conventions: zero when ab <= 0; min(x, y) follows x when x <= y;
+// max(m1, m2) follows m1 when m1 >= m2.  (a and b share their sign when
+// ab > 0, so the sign factors cancel in the derivatives.)  The value is
+// the max-min form itself; for beta >= 1 it equals sweby() bit for bit.
 template <typename T>
-__device__ __forceinline__ void sweby_d(T a, T b, T beta, T& da, T& db) {
-  T aa = fabs(a), ab = fabs(b);
-  T bb = beta * ab, ba = beta * aa;
-  bool m1a = aa <= bb;               // m1 = |a| (else beta |b|)
-  bool m2a = ba <= ab;               // m2 = beta |a| (else |b|)
-  T m1 = m1a ? aa : bb;
-  T m2 = m2a ? ba : ab;
-  bool first = m1 >= m2;
-  T d1a = m1a ? T(1) : T(0), d1b = m1a ? T(0) : beta;
-  T d2a = m2a ? beta : T(0), d2b = m2a ? T(0) : T(1);
-  bool act = a * b > T(0);
-  da = act ? (first ? d1a : d2a) : T(0);
-  db = act ? (first ? d1b : d2b) : T(0);
+__device__ __forceinline__ void sweby_all(T a, T b, T beta, T& phi, T& da, T& db) {
+  const T aa = fabs(a), ab = fabs(b);
+  const T ba = beta * aa, bb = beta * ab;
+  const T m1 = fmin(aa, bb);   // min(|a|, beta |b|)
+  const T m2 = fmin(ba, ab);   // min(beta |a|, |b|)
+  const bool act = a * b > T(0);
+  const bool m1a = aa <= bb;   // m1 follows |a|
+  const bool m2a = ba <= ab;   // m2 follows beta |a|
+  const bool first = m1 >= m2; // max follows m1
+  phi = act ? copysign(fmax(m1, m2), a) : T(0);
+  const bool a1 = act && first && m1a, a2 = act && !first && m2a;
+  const bool b1 = act && first && !m1a, b2 = act && !first && !m2a;
+  da = a1 ? T(1) : (a2 ? beta : T(0));
+  db = b1 ? beta : (b2 ? T(1) : T(0));
 }
 
 // ---- face flux: Lagrangian HLL solve (eqs. (13)-(14)) + upwind + eq. (12) --
@@ -215,65 +217,70 @@ __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceSt
 }
 
 // Vector-Jacobian product of face_flux: given the flux cotangent Fb,
-// returns the cotangents of the two face states.  Conventions at the
-// kinks: max(c_L^2, c_R^2) follows L on ties; the upwind side is L iff
-// u* > 0 (as in the forward).
+// returns the cotangents of the two face states.  The forward values are
+// recomputed exactly as face_flux() forms them.  Conventions at the kinks:
+// max(c_L, c_R) follows L on ties (p_L rho_R >= p_R rho_L); the upwind side
+// is L iff u* > 0.  Every division goes through one reciprocal and one
+// reciprocal square root: with q = 1/(rho_s S), 1/S = rho_s q,
+// 1/rho_s = S q, and da/dp_s = a/(2 p_s) = gamma/(2 rho_s a).
 template <typename T>
 __device__ __forceinline__ void face_flux_vjp(const FaceState<T>& L, const FaceState<T>& R,
                                               T gamma, T inv_gm1, const Flux<T>& Fb,
                                               FaceState<T>& Lb, FaceState<T>& Rb) {
-  T cl2 = gamma * L.p / L.r;
-  T cr2 = gamma * R.p / R.r;
-  bool aleft = cl2 >= cr2;
-  T a = sqrt(aleft ? cl2 : cr2);
-  T S = L.r + R.r;
-  T iS = T(1) / S;
-  T iS2 = iS * iS;
-  T B = L.r * R.r;
-  T Du = R.un - L.un;
-  T Dp = R.p - L.p;
-  T ps = (R.r * L.p + L.r * R.p) * iS - (B * iS) * a * Du;
-  T us = (L.r * L.un + R.r * R.un) * iS - iS * Dp / a;
-  bool left = us > T(0);
-  T r = left ? L.r : R.r;
-  T un = left ? L.un : R.un;
-  T ut = left ? L.ut : R.ut;
-  T p = left ? L.p : R.p;
-  T E = p * inv_gm1 + T(0.5) * r * (un * un + ut * ut);
+  const bool aleft = L.p * R.r >= R.p * L.r;
+  const T ps_ = aleft ? L.p : R.p;
+  const T rs_ = aleft ? L.r : R.r;
+  const T S = L.r + R.r;
+  const T q = rcp(rs_ * S);
+  const T iS = rs_ * q;
+  const T irs = S * q;
+  const T a2 = gamma * ps_ * irs;
+  const T ia = rsq(a2);
+  const T a = a2 * ia;
+  const T iS2 = iS * iS;
+  const T B = L.r * R.r;
+  const T Du = R.un - L.un;
+  const T Dp = R.p - L.p;
+  const T ps = fma(-(B * iS) * a, Du, fma(R.r, L.p, L.r * R.p) * iS);
+  const T us = fma(-Dp, iS * ia, fma(L.r, L.un, R.r * R.un) * iS);
+  const bool left = us > T(0);
+  const T r = left ? L.r : R.r;
+  const T un = left ? L.un : R.un;
+  const T ut = left ? L.ut : R.ut;
+  const T p = left ? L.p : R.p;
+  const T q2 = fma(un, un, ut * ut);
+  const T E = fma(T(0.5) * r, q2, p * inv_gm1);
 
   // through eq. (12) and the upwind state
-  T Eb = Fb.f3 * us;
-  T usb = Fb.f0 * r + Fb.f1 * r * un + Fb.f2 * r * ut + Fb.f3 * (E + ps);
-  T psb = Fb.f1 + Fb.f3 * us;
-  T rb = Fb.f0 * us + Fb.f1 * us * un + Fb.f2 * us * ut + Eb * T(0.5) * (un * un + ut * ut);
-  T unb = Fb.f1 * r * us + Eb * r * un;
-  T utb = Fb.f2 * r * us + Eb * r * ut;
-  T pb = Eb * inv_gm1;
+  const T Eb = Fb.f3 * us;
+  const T usb = fma(Fb.f3, E + ps, r * fma(Fb.f2, ut, fma(Fb.f1, un, Fb.f0)));
+  const T psb = fma(Fb.f3, us, Fb.f1);
+  const T rb = fma(Eb * T(0.5), q2, us * fma(Fb.f2, ut, fma(Fb.f1, un, Fb.f0)));
+  const T unb = r * fma(Fb.f1, us, Eb * un);
+  const T utb = r * fma(Fb.f2, us, Eb * ut);
+  const T pb = Eb * inv_gm1;
 
   // through eqs. (13)-(14)
-  T ab = psb * (-B * iS * Du) + usb * (iS * Dp / (a * a));
-  T rlb = psb * (R.r * Dp * iS2 - R.r * R.r * iS2 * a * Du) + usb * (-R.r * Du * iS2 + Dp * iS2 / a);
-  T rrb = psb * (-L.r * Dp * iS2 - L.r * L.r * iS2 * a * Du) + usb * (L.r * Du * iS2 + Dp * iS2 / a);
-  T unlb = psb * (B * iS * a) + usb * (L.r * iS);
-  T unrb = psb * (-B * iS * a) + usb * (R.r * iS);
-  T plb = psb * (R.r * iS) + usb * (iS / a);
-  T prb = psb * (L.r * iS) - usb * (iS / a);
-  // a = sqrt(gamma p_s / rho_s): da/dp = a / (2p), da/drho = -a / (2 rho)
-  if (aleft) {
-    rlb += ab * (-a / (T(2) * L.r));
-    plb += ab * (a / (T(2) * L.p));
-  } else {
-    rrb += ab * (-a / (T(2) * R.r));
-    prb += ab * (a / (T(2) * R.p));
-  }
-  Lb.r = rlb + (left ? rb : T(0));
+  const T BiSa = B * iS * a;
+  const T ab = fma(psb, -(B * iS) * Du, usb * (iS * Dp * ia * ia));
+  const T t1 = Dp * iS2 * ia;  // (p_R - p_L) / (S^2 a)
+  const T rlb = fma(psb, R.r * iS2 * (Dp - R.r * a * Du), usb * fma(-R.r * Du, iS2, t1));
+  const T rrb = fma(psb, -L.r * iS2 * (Dp + L.r * a * Du), usb * fma(L.r * Du, iS2, t1));
+  const T unlb = fma(psb, BiSa, usb * (L.r * iS));
+  const T unrb = fma(-psb, BiSa, usb * (R.r * iS));
+  const T plb = fma(psb, R.r * iS, usb * (iS * ia));
+  const T prb = fma(psb, L.r * iS, -usb * (iS * ia));
+  // a = sqrt(gamma p_s / rho_s)
+  const T dar = ab * (T(-0.5) * a * irs);
+  const T dap = ab * (T(0.5) * gamma * irs * ia);
+  Lb.r = rlb + (aleft ? dar : T(0)) + (left ? rb : T(0));
   Lb.un = unlb + (left ? unb : T(0));
   Lb.ut = left ? utb : T(0);
-  Lb.p = plb + (left ? pb : T(0));
-  Rb.r = rrb + (left ? T(0) : rb);
+  Lb.p = plb + (aleft ? dap : T(0)) + (left ? pb : T(0));
+  Rb.r = rrb + (aleft ? T(0) : dar) + (left ? T(0) : rb);
   Rb.un = unrb + (left ? T(0) : unb);
   Rb.ut = left ? T(0) : utb;
-  Rb.p = prb + (left ? T(0) : pb);
+  Rb.p = prb + (aleft ? T(0) : dap) + (left ? T(0) : pb);
 }
 
 // ---- wave-level reductions --------------------------------------------------
