@@ -70,3 +70,35 @@ def test_vortex_rounding_floor_256(oracle_lib):
 def test_vortex_rounding_floor_512(oracle_lib):
     peak = _vortex_floor(oracle_lib, 512)
     assert peak[0] > 1e-12 and np.all(peak < 1e-11), peak
+
+
+def _tube_floor(oracle_lib, name, n):
+    """Final relative L-infinity and L1 distance between the oracle's run
+    of a paper shock tube and the same run with one-ulp noise added after
+    every step."""
+    U, cfg = workloads.paper_tube(name, n)
+    P = params_from(cfg)
+    rng = np.random.default_rng(0)
+    A, B, t = U.copy(), U.copy(), 0.0
+    while t < cfg["t_end"]:
+        rc, dt = oracle_lib.dt(P, A)
+        last = dt >= cfg["t_end"] - t
+        dt = cfg["t_end"] - t if last else dt
+        A = oracle_lib.step(P, A, dt)
+        B = oracle_lib.step(P, B, dt)
+        B = B + np.spacing(B) * rng.choice([-1.0, 0.0, 1.0], size=B.shape)
+        t = cfg["t_end"] if last else t + dt
+    l1 = np.array([np.abs(B[f] - A[f]).sum() / max(np.abs(A[f]).sum(), np.abs(A[1]).sum())
+                   for f in range(4)])
+    return _rel_linf(B, A), l1
+
+
+@pytest.mark.parametrize("name,n", [("sod", 100), ("two_rarefaction", 200),
+                                    ("sonic_rarefaction", 400), ("shock_shock", 400)])
+def test_paper_tube_rounding_floor(oracle_lib, name, n):
+    """The one-dimensional tubes of the paper (single row, CFL 0.25, up to
+    ~1600 steps here): the floor stays below 2.5e-11 / 2.5e-12, a quarter
+    of the GPU parity bar for these runs (1e-10 / 1e-11)."""
+    linf, l1 = _tube_floor(oracle_lib, name, n)
+    assert np.all(linf < 2.5e-11), linf
+    assert np.all(l1 < 2.5e-12), l1

@@ -246,3 +246,33 @@ def kelvin_helmholtz_torch(n: int, *, device="cuda", dtype=None, gamma: float = 
     U[3] = 2.5 / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
     cfg = _cfg(n, n, 1.0, 1.0, PERIODIC, PERIODIC, gamma, 0.5, 1.5, steps=500)
     return U, cfg
+
+
+# ---- the paper's one-dimensional shock tubes ----------------------------------
+
+# name: (left (rho,u,p), right (rho,u,p), final time, cells, Sweby beta)
+# Sod, two-rarefaction near vacuum, sonic rarefaction with supersonic contact
+# (the text gives T = 0.16, a caption 0.18; 0.16 is used), shock-shock with
+# a Mach-40 right state and the minmod limiter (beta = 1).
+PAPER_TUBES = {
+    "sod": ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.23, (100, 400), 1.5),
+    "two_rarefaction": ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 0.16, (200, 2000), 1.5),
+    "sonic_rarefaction": ((5.0, 0.0, 5.0), (0.125, 0.0, 0.1), 0.16, (400,), 1.5),
+    "shock_shock": ((1.0, 5.0, 1.0), (1.0, -5.0, 0.01), 0.16, (400,), 1.0),
+}
+
+
+def paper_tube(name: str, n: int, *, gamma: float = 1.4, cfl: float = 0.25):
+    """One of the paper's shock tubes on [0,1] with n cells in a single row.
+    The row's cell is very tall (dy = 1e3), so the CFL sum
+    (|u|+c)/dx + (|v|+c)/dy is the one-dimensional (|u|+c)/dx to 1e-5
+    relative and CFL 0.25 means what it means in one dimension."""
+    left, right, t_end, _, beta = PAPER_TUBES[name]
+    x = cell_centres(n, 0.0, 1.0)
+    lo = x < 0.5
+    rho = np.where(lo, left[0], right[0])[None, :]
+    u = np.where(lo, left[1], right[1])[None, :]
+    p = np.where(lo, left[2], right[2])[None, :]
+    cfg = dict(nx=n, ny=1, dx=1.0 / n, dy=1.0e3, gamma=gamma, cfl=cfl, beta=beta,
+               bc_x=TRANSMISSIVE, bc_y=TRANSMISSIVE, t_end=t_end, left=left, right=right)
+    return prim_to_cons(gamma, rho, u, 0.0, p), cfg
