@@ -6,13 +6,14 @@ product path (``paper_1607_08710_amd``) never imports it, and the two share
 no code: the oracle is the C file ``lfo.c`` next to this module, loaded
 here through ctypes.
 
-Arrays are numpy float64, C-contiguous, shape (4, ny, nx) with the fields
-(rho, rho*u, rho*v, rho*E) and x fastest.
+Arrays are numpy float64, C-contiguous, shape (4 + ns, ny, nx) with the
+fields (rho, rho*u, rho*v, rho*E, rho*y_1, ..., rho*y_ns) and x fastest.
 
 Functions follow the paper (De Vuyst et al., arXiv:1607.08710): the
 Euler system and perfect-gas EOS of Sec. 3, the semi-discrete flux form of
 eqs. (11)-(12), the Sweby limiter of eq. (sweby), the Lagrangian HLL solver
-of eqs. (13)-(14) and the Heun predictor-corrector list of Sec. 5.
+of eqs. (13)-(14) and the Heun predictor-corrector list of Sec. 5, plus
+the conservative transport of passive mass fractions of Sec. 7.
 """
 from __future__ import annotations
 
@@ -53,6 +54,7 @@ class _Params(ctypes.Structure):
         ("dx", ctypes.c_double), ("dy", ctypes.c_double),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("beta", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("ns", ctypes.c_int32),
     ]
 
 
@@ -67,10 +69,11 @@ class Params:
     beta: float = 1.5
     bc_x: int = PERIODIC
     bc_y: int = PERIODIC
+    ns: int = 0  # passive mass fractions: fields 4 .. 3+ns hold rho*y_k
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.dx, self.dy, self.gamma, self.cfl,
-                       self.beta, self.bc_x, self.bc_y)
+                       self.beta, self.bc_x, self.bc_y, self.ns)
 
     def with_(self, **kw) -> "Params":
         d = dict(self.__dict__)
@@ -123,8 +126,8 @@ def _ptr(a: np.ndarray):
 
 def _state(P: Params, U) -> np.ndarray:
     U = np.ascontiguousarray(U, dtype=np.float64)
-    if U.shape != (4, P.ny, P.nx):
-        raise ValueError(f"state shape {U.shape} != (4, {P.ny}, {P.nx})")
+    if U.shape != (4 + P.ns, P.ny, P.nx):
+        raise ValueError(f"state shape {U.shape} != ({4 + P.ns}, {P.ny}, {P.nx})")
     return U
 
 
@@ -201,7 +204,7 @@ def advance(P: Params, U, t0: float, t_end: float, max_steps: int = 10**9,
 
 def totals(P: Params, U) -> np.ndarray:
     U = _state(P, U)
-    out = np.empty(4)
+    out = np.empty(4 + P.ns)
     lib().lfo_totals(ctypes.byref(P.c()), _ptr(U), _ptr(out))
     return out
 

@@ -245,13 +245,15 @@ static int check_params(const lfo_params *P)
     if (!(P->gamma > 1.0 && P->gamma <= 3.0)) return 0;
     if (!(P->beta >= 0.0 && P->beta <= 2.0)) return 0;
     if (!(P->cfl > 0.0)) return 0;
+    if (P->ns < 0 || P->ns > LFO_MAX_SPECIES) return 0;
     if ((P->bc_x != LFO_BC_PERIODIC && P->bc_x != LFO_BC_TRANSMISSIVE) ||
         (P->bc_y != LFO_BC_PERIODIC && P->bc_y != LFO_BC_TRANSMISSIVE))
         return 0;
     return 1;
 }
 
-/* Primitive variables of every cell, layout w[v][j][i]. */
+/* Primitive variables of every cell, layout w[v][j][i]: (rho, u, v, p)
+ * followed by the mass fractions y_k = (rho y_k) / rho. */
 static void all_prims(const lfo_params *P, const double *U, double *w)
 {
     const int64_t N = (int64_t)P->nx * P->ny;
@@ -262,7 +264,33 @@ static void all_prims(const lfo_params *P, const double *U, double *w)
         lfo_cons_to_prim(P->gamma, Uq, wq);
         for (int v = 0; v < 4; ++v)
             w[v * N + q] = wq[v];
+        for (int k = 0; k < P->ns; ++k)
+            w[(4 + k) * N + q] = U[(4 + k) * N + q] / U[q];
     }
+}
+
+/* Flux of rho y_k through one face (Sec. 7, conservative form of the mass
+ * fraction transport, discretised like the mass flux of eq. (12)).  W is
+ * the face-frame Euler stencil of stencil_face() and Y the mass fraction
+ * of the same four cells.  Both y and the Euler variables are
+ * reconstructed with the limited slopes of Sec. 5; the acoustic solve of
+ * eqs. (13)-(14) on the reconstructed states gives u*, the upwind side A
+ * is the left one when u* > 0, and the flux is (rho_A y_A) u*. */
+static double species_face_flux(double gamma, double beta, const double W[4][4],
+                                const double Y[4])
+{
+    double wl[4], wr[4];
+    for (int v = 0; v < 4; ++v) {
+        wl[v] = W[1][v] + 0.5 * lfo_sweby(W[1][v] - W[0][v], W[2][v] - W[1][v], beta);
+        wr[v] = W[2][v] - 0.5 * lfo_sweby(W[2][v] - W[1][v], W[3][v] - W[2][v], beta);
+    }
+    double yl = Y[1] + 0.5 * lfo_sweby(Y[1] - Y[0], Y[2] - Y[1], beta);
+    double yr = Y[2] - 0.5 * lfo_sweby(Y[2] - Y[1], Y[3] - Y[2], beta);
+    double us, ps;
+    lfo_acoustic_solve(gamma, wl[0], wl[1], wl[3], wr[0], wr[1], wr[3], &us, &ps);
+    if (us > 0.0)
+        return (wl[0] * yl) * us;
+    return (wr[0] * yr) * us;
 }
 
 /* Face-frame stencil of x-face k (between cells k-1 and k of row j):
@@ -309,14 +337,14 @@ static const int YFIELD[4] = {0, 2, 1, 3};
 int lfo_residual(const lfo_params *P, const double *U, double *R)
 {
     if (!check_params(P) || !U || !R) return LFO_ERR_ARG;
-    const int nx = P->nx, ny = P->ny;
+    const int nx = P->nx, ny = P->ny, nf = 4 + P->ns;
     const int64_t N = (int64_t)nx * ny;
-    double *w = (double *)malloc(sizeof(double) * 4 * N);
+    double *w = (double *)malloc(sizeof(double) * nf * N);
     /* Fx[c][j][k], k = 0..nx: x-face between cells k-1 and k.
      * Gy[c][k][i], k = 0..ny: y-face between cells k-1 and k. */
     const int64_t NFx = (int64_t)ny * (nx + 1), NGy = (int64_t)(ny + 1) * nx;
-    double *Fx = (double *)malloc(sizeof(double) * 4 * NFx);
-    double *Gy = (double *)malloc(sizeof(double) * 4 * NGy);
+    double *Fx = (double *)malloc(sizeof(double) * nf * NFx);
+    double *Gy = (double *)malloc(sizeof(double) * nf * NGy);
     if (!w || !Fx || !Gy) { free(w); free(Fx); free(Gy); return LFO_ERR_ARG; }
 
     all_prims(P, U, w);
@@ -330,6 +358,13 @@ int lfo_residual(const lfo_params *P, const double *U, double *R)
             stencil_face(P->gamma, P->beta, W, phi, NULL);
             for (int c = 0; c < 4; ++c)
                 Fx[XFIELD[c] * NFx + (int64_t)j * (nx + 1) + k] = phi[c];
+            for (int sp = 0; sp < P->ns; ++sp) {
+                double Y[4];
+                for (int t = 0; t < 4; ++t)
+                    Y[t] = w[(4 + sp) * N + cell[t]];
+                Fx[(4 + sp) * NFx + (int64_t)j * (nx + 1) + k] =
+                    species_face_flux(P->gamma, P->beta, W, Y);
+            }
         }
     }
 #pragma omp parallel for schedule(static)
@@ -341,12 +376,19 @@ int lfo_residual(const lfo_params *P, const double *U, double *R)
             stencil_face(P->gamma, P->beta, W, phi, NULL);
             for (int c = 0; c < 4; ++c)
                 Gy[YFIELD[c] * NGy + (int64_t)k * nx + i] = phi[c];
+            for (int sp = 0; sp < P->ns; ++sp) {
+                double Y[4];
+                for (int t = 0; t < 4; ++t)
+                    Y[t] = w[(4 + sp) * N + cell[t]];
+                Gy[(4 + sp) * NGy + (int64_t)k * nx + i] =
+                    species_face_flux(P->gamma, P->beta, W, Y);
+            }
         }
     }
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
-            for (int f = 0; f < 4; ++f) {
+            for (int f = 0; f < nf; ++f) {
                 double fe = Fx[f * NFx + (int64_t)j * (nx + 1) + i + 1];
                 double fw = Fx[f * NFx + (int64_t)j * (nx + 1) + i];
                 double gn = Gy[f * NGy + (int64_t)(j + 1) * nx + i];
@@ -400,7 +442,7 @@ int lfo_dt(const lfo_params *P, const double *U, double *dt)
 int lfo_step(const lfo_params *P, const double *Un, double dt, double *Unp1)
 {
     if (!check_params(P) || !Un || !Unp1) return LFO_ERR_ARG;
-    const int64_t M = 4 * (int64_t)P->nx * P->ny;
+    const int64_t M = (4 + P->ns) * (int64_t)P->nx * P->ny;
     double *Rn = (double *)malloc(sizeof(double) * M);
     double *Us = (double *)malloc(sizeof(double) * M);
     double *Rs = (double *)malloc(sizeof(double) * M);
@@ -427,7 +469,7 @@ int lfo_advance(const lfo_params *P, double *U, double t0, double t_end,
                 int64_t max_steps, double *t_out, int64_t *steps_out, double *dts)
 {
     if (!check_params(P) || !U) return LFO_ERR_ARG;
-    const int64_t M = 4 * (int64_t)P->nx * P->ny;
+    const int64_t M = (4 + P->ns) * (int64_t)P->nx * P->ny;
     double *Unew = (double *)malloc(sizeof(double) * M);
     if (!Unew) return LFO_ERR_ARG;
     double t = t0;
@@ -458,10 +500,10 @@ int lfo_advance(const lfo_params *P, double *U, double t0, double t_end,
     return rc;
 }
 
-void lfo_totals(const lfo_params *P, const double *U, double out[4])
+void lfo_totals(const lfo_params *P, const double *U, double *out)
 {
     const int64_t N = (int64_t)P->nx * P->ny;
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 4 + P->ns; ++f) {
         double s = 0.0, comp = 0.0; /* Neumaier compensated sum */
         for (int64_t q = 0; q < N; ++q) {
             double x = U[f * N + q];
@@ -517,6 +559,7 @@ static void prim_tangent(const lfo_params *P, const double *U, const double *dU,
 int lfo_residual_jvp(const lfo_params *P, const double *U, const double *dU, double *out)
 {
     if (!check_params(P) || !U || !dU || !out) return LFO_ERR_ARG;
+    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
     const int nx = P->nx, ny = P->ny;
     const int64_t N = (int64_t)nx * ny;
     const int64_t NFx = (int64_t)ny * (nx + 1), NGy = (int64_t)(ny + 1) * nx;
@@ -582,6 +625,7 @@ int lfo_residual_jvp(const lfo_params *P, const double *U, const double *dU, dou
 int lfo_residual_vjp(const lfo_params *P, const double *U, const double *g, double *out)
 {
     if (!check_params(P) || !U || !g || !out) return LFO_ERR_ARG;
+    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
     const int nx = P->nx, ny = P->ny;
     const int64_t N = (int64_t)nx * ny;
     double *w = (double *)malloc(sizeof(double) * 4 * N);
@@ -661,6 +705,7 @@ int lfo_tlm_step(const lfo_params *P, const double *Un, double dt,
                  const double *dUn, double *dUnp1)
 {
     if (!check_params(P) || !Un || !dUn || !dUnp1) return LFO_ERR_ARG;
+    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
     const int64_t M = 4 * (int64_t)P->nx * P->ny;
     double *Rn = (double *)malloc(sizeof(double) * M);
     double *Us = (double *)malloc(sizeof(double) * M);
@@ -692,6 +737,7 @@ int lfo_adjoint_step(const lfo_params *P, const double *Un, double dt,
                      const double *lam_np1, double *lam_n)
 {
     if (!check_params(P) || !Un || !lam_np1 || !lam_n) return LFO_ERR_ARG;
+    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
     const int64_t M = 4 * (int64_t)P->nx * P->ny;
     double *Rn = (double *)malloc(sizeof(double) * M);
     double *Us = (double *)malloc(sizeof(double) * M);

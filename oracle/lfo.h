@@ -27,6 +27,12 @@
  *  - Boundary conditions per axis: periodic (index wrap) or transmissive
  *    (index clamp: ghost cells copy the edge cell).
  *  - Upwind side: left when u* > 0, right otherwise.
+ *  - Passive mass fractions (the conservative transport equations of
+ *    rho y_k, Sec. 7): y_k = (rho y_k) / rho is reconstructed like the other
+ *    primitive variables, and the flux through a face is (rho_A y_k,A) u*
+ *    with A the same upwind side and rho_A the reconstructed density of
+ *    that side.  A single gamma for the mixture (the paper gives no mixture
+ *    law).
  */
 #ifndef LFO_H
 #define LFO_H
@@ -49,7 +55,12 @@ typedef struct {
     double cfl;          /* CFL number used by lfo_dt, > 0                   */
     double beta;         /* Sweby limiter coefficient, in [0, 2]             */
     int32_t bc_x, bc_y;  /* LFO_BC_PERIODIC or LFO_BC_TRANSMISSIVE          */
+    int32_t ns;          /* passive mass fractions, 0..LFO_MAX_SPECIES: the
+                            state then holds 4 + ns fields, field 4 + k
+                            being rho y_k                                    */
 } lfo_params;
+
+#define LFO_MAX_SPECIES 8
 
 /* ---- pointwise pieces (Sec. 3 EOS; eq. (sweby); eqs. (13)-(14); eq. (12)) */
 
@@ -95,13 +106,14 @@ int lfo_advance(const lfo_params *P, double *U, double t0, double t_end,
                 int64_t max_steps, double *t_out, int64_t *steps_out,
                 double *dts);
 
-/* Compensated (Neumaier) sums of each field times dx*dy. */
-void lfo_totals(const lfo_params *P, const double *U, double out[4]);
+/* Compensated (Neumaier) sums of each of the 4 + ns fields times dx*dy. */
+void lfo_totals(const lfo_params *P, const double *U, double *out);
 
 /* ---- linearisation of the step at frozen dt ----------------------------- */
 
 /* Jacobian-vector product J_R(U) dU, and vector-Jacobian product
- * J_R(U)^T g, of the residual R. */
+ * J_R(U)^T g, of the residual R.  These and the tangent-linear and adjoint
+ * steps below cover the Euler fields only: LFO_ERR_ARG when ns > 0. */
 int lfo_residual_jvp(const lfo_params *P, const double *U, const double *dU,
                      double *out);
 int lfo_residual_vjp(const lfo_params *P, const double *U, const double *g,

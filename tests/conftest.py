@@ -24,7 +24,8 @@ def oracle_lib():
 def params_from(cfg, **over):
     import oracle
     kw = dict(nx=cfg["nx"], ny=cfg["ny"], dx=cfg["dx"], dy=cfg["dy"], gamma=cfg["gamma"],
-              cfl=cfg["cfl"], beta=cfg["beta"], bc_x=cfg["bc_x"], bc_y=cfg["bc_y"])
+              cfl=cfg["cfl"], beta=cfg["beta"], bc_x=cfg["bc_x"], bc_y=cfg["bc_y"],
+              ns=cfg.get("ns", 0))
     kw.update(over)
     return oracle.Params(**kw)
 

@@ -276,3 +276,55 @@ def paper_tube(name: str, n: int, *, gamma: float = 1.4, cfl: float = 0.25):
     cfg = dict(nx=n, ny=1, dx=1.0 / n, dy=1.0e3, gamma=gamma, cfl=cfl, beta=beta,
                bc_x=TRANSMISSIVE, bc_y=TRANSMISSIVE, t_end=t_end, left=left, right=right)
     return prim_to_cons(gamma, rho, u, 0.0, p), cfg
+
+
+# ---- passive mass fractions (conservative transport of rho*y_k, Sec. 7) -------
+
+def with_fractions(U, ys):
+    """State with the fields rho*y_k appended: U has the 4 Euler fields,
+    ys is a list of mass-fraction arrays broadcastable to U[0]."""
+    out = np.empty((4 + len(ys),) + U.shape[1:], dtype=U.dtype)
+    out[:4] = U
+    for k, y in enumerate(ys):
+        out[4 + k] = U[0] * np.broadcast_to(y, U.shape[1:])
+    return out
+
+
+def sod_interface(n: int = 400, ny: int = 4, **kw):
+    """Sod 400x4 (CFL 0.5, t = 0.2) carrying two materials: y_1 = 1 left of
+    the diaphragm, y_2 = 1 - y_1, stored as rho*y_2 = rho - rho*y_1."""
+    U, cfg = sod(n, ny, **kw)
+    x = cell_centres(n, 0.0, 1.0)[None, :]
+    y1 = np.where(x < 0.5, 1.0, 0.0) * np.ones((ny, 1))
+    out = with_fractions(U, [y1])
+    out = np.concatenate([out, (out[0] - out[4])[None]], axis=0)
+    cfg = dict(cfg, ns=2)
+    return out, cfg
+
+
+def advected_fraction(nx: int, ny: int, u: float, v: float, seed: int, *, bc=(PERIODIC, PERIODIC),
+                      beta: float = 1.5, rho: float = 1.3, p: float = 0.9, cfl: float = 0.4):
+    """Uniform rho, p and velocity (u, v) carrying one rough mass fraction
+    (independent uniform draws in [0, 1]): the Euler fields are a fixed
+    point and the fraction is linearly advected."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    y = rng.uniform(0.0, 1.0, (ny, nx))
+    U = prim_to_cons(1.4, np.full((ny, nx), rho), u, v, p)
+    cfg = _cfg(nx, ny, 1.0, ny / nx, bc[0], bc[1], 1.4, cfl, beta, ns=1)
+    return with_fractions(U, [y]), cfg
+
+
+def random_state_fractions(nx: int, ny: int, ns: int, seed: int, **kw):
+    """random_state() plus ns rough mass fractions in [0, 1]."""
+    U = random_state(nx, ny, seed, **kw)
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    return with_fractions(U, [rng.uniform(0.0, 1.0, (ny, nx)) for _ in range(ns)])
+
+
+def kelvin_helmholtz_fraction(n: int, **kw):
+    """kelvin_helmholtz() with one material marker: y = 1 inside the band
+    |y - 1/2| < 1/4, 0 outside."""
+    U, cfg = kelvin_helmholtz(n, **kw)
+    yc = cell_centres(n, 0.0, 1.0)
+    marker = np.where(np.abs(yc - 0.5) < 0.25, 1.0, 0.0)[:, None]
+    return with_fractions(U, [marker]), dict(cfg, ns=1)
