@@ -10,12 +10,21 @@
  * eq. (12); per cell, the conservative update of eq. (11) inside the Heun
  * predictor-corrector of Sec. 5, with dt from a global CFL reduction.
  *
+ * A state may also carry passive mass fractions y_k (the conservative
+ * transport of rho y_k that the paper prefers for multimaterial flow,
+ * Sec. 7): each y_k is reconstructed like the primitive variables and
+ * crosses a face with the face mass flux of its upwind side, (rho_A u*)
+ * y_k,A, so a uniform fraction stays uniform and every rho y_k is
+ * conserved.  One gamma holds for the whole mixture.
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - State arrays are DEVICE pointers owned by the caller, contiguous, in
  *    structure-of-arrays layout U[f][j][i]: f = 0..3 for (rho, rho*u, rho*v,
- *    rho*E), j = 0..ny-1 the y index, i = 0..nx-1 the x index (fastest).
- *    Element type is double (LF_F64) or float (LF_F32), per the context.
+ *    rho*E), then f = 4..3+n_species for rho*y_k; j = 0..ny-1 the y index,
+ *    i = 0..nx-1 the x index (fastest).  Element type is double (LF_F64) or
+ *    float (LF_F32), per the context.  The adjoint entry points take the 4
+ *    Euler fields only and require n_species == 0.
  *  - ws is a DEVICE workspace of at least the size lf_init reports, owned
  *    by the caller, 256-byte aligned.  It holds the predictor state U*, the
  *    adjoint intermediate, the reduction cells and the device-side dt / t /
@@ -51,6 +60,8 @@ typedef enum {
 } lf_status;
 
 typedef enum { LF_F64 = 0, LF_F32 = 1 } lf_dtype;
+
+#define LF_MAX_SPECIES 4
 typedef enum { LF_BC_PERIODIC = 0, LF_BC_TRANSMISSIVE = 1 } lf_bc;
 
 typedef struct {
@@ -65,6 +76,8 @@ typedef struct {
                          clamps it (ghost cells copy the edge cell)             */
     int32_t bc_y;     /* lf_bc along y                                          */
     int32_t dtype;    /* lf_dtype of every state / adjoint array                */
+    int32_t n_species; /* passive mass fractions carried after the Euler
+                         fields, 0 <= n_species <= LF_MAX_SPECIES            */
 } lf_params;
 
 /* Validates *params, creates a context and reports the workspace size in
@@ -122,7 +135,8 @@ int lf_advance(lf_ctx *ctx, void *U, double t0, double t_end, int64_t max_steps,
  * not overlap U. */
 int lf_residual(lf_ctx *ctx, const void *U, void *R, void *ws, void *stream);
 
-/* Vector-Jacobian product out = J_R(U)^T g of the residual, async.  The
+/* Vector-Jacobian product out = J_R(U)^T g of the residual, async
+ * (contexts without mass fractions; LF_ERR_ARG otherwise).  The
  * derivative conventions at the non-differentiable points are: limiter
  * derivative zero when ab <= 0, min follows its first argument on ties,
  * max(m1, m2) follows m1 on ties, max(c_L, c_R) follows c_L on ties, the
@@ -130,7 +144,8 @@ int lf_residual(lf_ctx *ctx, const void *U, void *R, void *ws, void *stream);
 int lf_residual_vjp(lf_ctx *ctx, const void *U, const void *g, void *out, void *ws,
                     void *stream);
 
-/* Adjoint of one lf_step at the frozen dt, async: given lam_np1 =
+/* Adjoint of one lf_step at the frozen dt, async (contexts without mass
+ * fractions; LF_ERR_ARG otherwise): given lam_np1 =
  * dJ/dU^{n+1}, writes lam_n = dJ/dU^n, recomputing U* from Un:
  *   mu    = (lam_np1 - dt J_R(U*)^T lam_np1) / 2
  *   lam_n = lam_np1 / 2 + mu - dt J_R(U^n)^T mu.
@@ -138,9 +153,10 @@ int lf_residual_vjp(lf_ctx *ctx, const void *U, const void *g, void *out, void *
 int lf_adjoint_step(lf_ctx *ctx, const void *Un, double dt, const void *lam_np1,
                     void *lam_n, void *ws, void *stream);
 
-/* Conservation totals: out[f] = dx*dy * sum_K U_f(K), summed in FP64 with
- * compensation in a fixed order (deterministic).  Synchronises. */
-int lf_totals(lf_ctx *ctx, const void *U, void *ws, void *stream, double out[4]);
+/* Conservation totals: out[f] = dx*dy * sum_K U_f(K) for the 4 + n_species
+ * fields (out has that many entries), summed in FP64 with compensation in
+ * a fixed order (deterministic).  Synchronises. */
+int lf_totals(lf_ctx *ctx, const void *U, void *ws, void *stream, double *out);
 
 #ifdef __cplusplus
 }

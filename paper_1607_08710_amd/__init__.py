@@ -6,9 +6,10 @@ HIP kernels of the library.  PyTorch provides device memory and the
 stream (``torch.cuda.current_stream()``).  There is no CPU fallback: if
 the library is missing or no GPU is present, the calls raise.
 
-State tensors: contiguous, shape (4, ny, nx), dtype float64 (LF_F64) or
-float32 (LF_F32), on the solver's device, holding (rho, rho*u, rho*v,
-rho*E) with x fastest.
+State tensors: contiguous, shape (4 + n_species, ny, nx), dtype float64
+(LF_F64) or float32 (LF_F32), on the solver's device, holding (rho, rho*u,
+rho*v, rho*E) and then rho*y_k for the n_species passive mass fractions,
+with x fastest.
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ LIB_PATH = os.path.join(_PKG, "liblagrangeflux.so")
 LF_OK, LF_ERR_ARG, LF_ERR_HIP, LF_ERR_NONPHYSICAL, LF_ERR_STATE = 0, 1, 2, 3, 4
 LF_F64, LF_F32 = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
+LF_MAX_SPECIES = 4
 
 # Names exported by the C ABI (include/lagrangeflux.h).
 ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_stage", "lf_advance",
@@ -46,6 +48,7 @@ class lf_params(ctypes.Structure):
         ("dx", ctypes.c_double), ("dy", ctypes.c_double),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("beta", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("n_species", ctypes.c_int32),
     ]
 
 
@@ -105,10 +108,11 @@ class Params:
     bc_x: int = PERIODIC
     bc_y: int = PERIODIC
     dtype: int = LF_F64
+    n_species: int = 0
 
     def c(self) -> lf_params:
         return lf_params(self.nx, self.ny, self.dx, self.dy, self.gamma, self.cfl, self.beta,
-                         self.bc_x, self.bc_y, self.dtype)
+                         self.bc_x, self.bc_y, self.dtype, self.n_species)
 
 
 def init(params: Params):
@@ -134,7 +138,7 @@ class Solver:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self.torch_dtype = torch.float64 if params.dtype == LF_F64 else torch.float32
-        self.shape = (4, params.ny, params.nx)
+        self.shape = (4 + params.n_species, params.ny, params.nx)
         self._ctx, self.ws_bytes = init(params)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
 
@@ -206,7 +210,7 @@ class Solver:
                                      self._stream()), "lf_adjoint_step")
 
     def totals(self, U) -> np.ndarray:
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * self.shape[0])()
         _check(lib().lf_totals(self._ctx, self._arg(U, "U"), ctypes.c_void_p(self.ws.data_ptr()),
                                self._stream(), out), "lf_totals")
         return np.array(out[:])

@@ -13,6 +13,8 @@
 #include "lagrangeflux.h"
 #include "lf_internal.h"
 
+static_assert(LF_MAX_SPECIES == lf::kMaxSpecies, "species cap of the ABI and the kernels");
+
 struct lf_ctx {
   lf::Grid g;
   lf::Layout L;
@@ -32,6 +34,7 @@ bool params_ok(const lf_params* p) {
   if (p->bc_x != LF_BC_PERIODIC && p->bc_x != LF_BC_TRANSMISSIVE) return false;
   if (p->bc_y != LF_BC_PERIODIC && p->bc_y != LF_BC_TRANSMISSIVE) return false;
   if (p->dtype != LF_F64 && p->dtype != LF_F32) return false;
+  if (p->n_species < 0 || p->n_species > LF_MAX_SPECIES) return false;
   return true;
 }
 
@@ -66,9 +69,9 @@ int lf_init(const lf_params* params, lf_ctx** out, size_t* workspace_bytes) {
   lf_ctx* c = new (std::nothrow) lf_ctx;
   if (!c) return LF_ERR_ARG;
   c->g = lf::make_grid(params->nx, params->ny, params->dx, params->dy, params->gamma, params->cfl,
-                       params->beta, params->bc_x, params->bc_y, params->dtype);
+                       params->beta, params->bc_x, params->bc_y, params->dtype, params->n_species);
   c->L = lf::make_layout(c->g);
-  c->state_bytes = 4 * (size_t)params->nx * (size_t)params->ny *
+  c->state_bytes = (size_t)(4 + params->n_species) * (size_t)params->nx * (size_t)params->ny *
                    (params->dtype == LF_F64 ? sizeof(double) : sizeof(float));
   *out = c;
   *workspace_bytes = c->L.total;
@@ -204,7 +207,7 @@ int lf_residual(lf_ctx* ctx, const void* U, void* R, void* ws, void* stream) {
 }
 
 int lf_residual_vjp(lf_ctx* ctx, const void* U, const void* g, void* out, void* ws, void* stream) {
-  if (!ctx || !U || !g || !out || !ws) return LF_ERR_ARG;
+  if (!ctx || !U || !g || !out || !ws || ctx->g.ns != 0) return LF_ERR_ARG;
   const size_t n = ctx->state_bytes;
   if (overlap(out, n, U, n) || overlap(out, n, g, n) || overlap(out, n, ws, ctx->L.total))
     return LF_ERR_ARG;
@@ -214,7 +217,7 @@ int lf_residual_vjp(lf_ctx* ctx, const void* U, const void* g, void* out, void* 
 
 int lf_adjoint_step(lf_ctx* ctx, const void* Un, double dt, const void* lam_np1, void* lam_n, void* ws,
                     void* stream) {
-  if (!ctx || !Un || !lam_np1 || !lam_n || !ws) return LF_ERR_ARG;
+  if (!ctx || !Un || !lam_np1 || !lam_n || !ws || ctx->g.ns != 0) return LF_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return LF_ERR_ARG;
   const size_t n = ctx->state_bytes, w = ctx->L.total;
   if (overlap(lam_n, n, Un, n) || overlap(lam_n, n, lam_np1, n)) return LF_ERR_ARG;
@@ -228,14 +231,14 @@ int lf_adjoint_step(lf_ctx* ctx, const void* Un, double dt, const void* lam_np1,
   return hip_status(e);
 }
 
-int lf_totals(lf_ctx* ctx, const void* U, void* ws, void* stream, double out[4]) {
+int lf_totals(lf_ctx* ctx, const void* U, void* ws, void* stream, double* out) {
   if (!ctx || !U || !ws || !out) return LF_ERR_ARG;
   if (overlap(U, ctx->state_bytes, ws, ctx->L.total)) return LF_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   lf::Ctl* ctl = ctl_of(ctx, ws);
   hipError_t e = lf::launch_totals(ctx->g, ctx->L, U, ws, s);
   if (e != hipSuccess) return LF_ERR_HIP;
-  e = hipMemcpyAsync(out, ctl->totals, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(out, ctl->totals, (size_t)(4 + ctx->g.ns) * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return LF_ERR_HIP;
   return hip_status(hipStreamSynchronize(s));
 }

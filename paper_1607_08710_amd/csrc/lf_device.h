@@ -24,6 +24,7 @@ template <typename T>
 constexpr int waves_per_block() { return sizeof(T) == 8 ? 4 : 8; }
 constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kDtHist = 4096;    // per-step dt records kept on the device
+constexpr int kMaxSpecies = 4;   // passive mass fractions a state may carry
 
 enum : int { kBcPeriodic = 0, kBcTransmissive = 1 };
 
@@ -43,7 +44,7 @@ struct Ctl {
   double cfl;
   unsigned int clamped;      // the step in flight was clamped to t_end
   unsigned int pad;
-  double totals[4];          // result of the conservation-totals reduction
+  double totals[4 + kMaxSpecies];  // result of the conservation-totals reduction
   double dt_hist[kDtHist];   // dt of step k stored at k % kDtHist
 };
 
@@ -182,9 +183,11 @@ struct Flux {
   T f0, f1, f2, f3;  // mass, normal momentum, tangential momentum, energy
 };
 
+// left_out receives the upwind side (true: left, u* > 0), which the
+// transport of the mass fractions shares.
 template <typename T>
 __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceState<T>& R,
-                                             T gamma, T inv_gm1) {
+                                             T gamma, T inv_gm1, bool& left_out) {
   // a = max(c_L, c_R): the side with the larger p/rho (compared as
   // p_L rho_R >= p_R rho_L, both densities positive) sets a^2 = gamma p/rho.
   const bool lside = L.p * R.r >= R.p * L.r;
@@ -202,6 +205,7 @@ __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceSt
   const T us = fma(-(R.p - L.p), iS * ia, fma(L.r, L.un, R.r * R.un) * iS);
   // upwind on the sign of u*: left when u* > 0
   const bool left = us > T(0);
+  left_out = left;
   const T r = left ? L.r : R.r;
   const T un = left ? L.un : R.un;
   const T ut = left ? L.ut : R.ut;
@@ -214,6 +218,13 @@ __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceSt
   F.f2 = m * ut;
   F.f3 = (E + ps) * us;
   return F;
+}
+
+template <typename T>
+__device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceState<T>& R,
+                                             T gamma, T inv_gm1) {
+  bool left;
+  return face_flux(L, R, gamma, inv_gm1, left);
 }
 
 // Vector-Jacobian product of face_flux: given the flux cotangent Fb,

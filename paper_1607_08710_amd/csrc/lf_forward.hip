@@ -88,9 +88,16 @@ __device__ __forceinline__ T combine(T q, T b, T res, double dt) {
   }
 }
 
-template <typename T, int MODE, int BCX, int BCY>
+// Mass fractions of one row (NS of them; one unused slot when NS = 0).
+template <typename T, int NS>
+struct Frac {
+  T v[NS > 0 ? NS : 1];
+};
+
+template <typename T, int MODE, int BCX, int BCY, int NS>
 __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(StageArgs<T> a) {
   constexpr int WPB = waves_per_block<T>();
+  constexpr int NF = 4 + NS;  // conservative fields: Euler, then rho*y_k
   if (a.dt_dev && a.ctl->done) return;
   const int lb = xcd_block(blockIdx.x, a.blocks_pad);
   if (lb >= a.blocks) return;  // whole block
@@ -109,30 +116,44 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
   const bool out_lane = lane >= kHalo && lane < kWave - kHalo && c < a.nx;
   const double dt = a.dt_dev ? a.ctl->dt : a.dt;
   const int nx = a.nx, ny = a.ny;
+  const long long plane = a.plane;
   const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta;
 
   const T* __restrict__ I0 = a.in;
-  const T* __restrict__ I1 = I0 + a.plane;
-  const T* __restrict__ I2 = I1 + a.plane;
-  const T* __restrict__ I3 = I2 + a.plane;
+  const T* __restrict__ I1 = I0 + plane;
+  const T* __restrict__ I2 = I1 + plane;
+  const T* __restrict__ I3 = I2 + plane;
+  const T* __restrict__ IS = I3 + plane;  // rho*y_k planes
 
-  auto load_row = [&](int row, T (&q)[4]) {
+  auto load_row = [&](int row, T (&q)[NF]) {
     const int off = map_index<BCY>(row, ny) * nx + cm;
     q[0] = I0[off];
     q[1] = I1[off];
     q[2] = I2[off];
     q[3] = I3[off];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) q[4 + s] = IS[s * plane + off];
   };
 
   T* O0 = a.out;
-  T* O1 = O0 + a.plane;
-  T* O2 = O1 + a.plane;
-  T* O3 = O2 + a.plane;
+  T* O1 = O0 + plane;
+  T* O2 = O1 + plane;
+  T* O3 = O2 + plane;
+  T* OS = O3 + plane;
   // base is nullptr unless MODE == kCorrector; only the corrector reads it
   const T* B0 = a.base;
-  const T* B1 = B0 + a.plane;
-  const T* B2 = B1 + a.plane;
-  const T* B3 = B2 + a.plane;
+  const T* B1 = B0 + plane;
+  const T* B2 = B1 + plane;
+  const T* B3 = B2 + plane;
+  const T* BS = B3 + plane;
+  auto load_base = [&](int off, T (&b)[NF]) {
+    b[0] = B0[off];
+    b[1] = B1[off];
+    b[2] = B2[off];
+    b[3] = B3[off];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) b[4 + s] = BS[s * plane + off];
+  };
 
   // Row pipeline.  While row o is finished, the stencil rows o+3 and o+4
   // are in flight (prefetch distance two rows) and the corrector's U^n rows
@@ -141,29 +162,42 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
   // reads back its own values, so no synchronisation is needed).  Slots
   // alternate between the even and odd rows of a strip; the loop is
   // unrolled by two so that they rotate by renaming.
-  __shared__ T ring[WPB][3][4][kWave];
-  T(*my)[4][kWave] = ring[w];
+  __shared__ T ring[WPB][3][NF][kWave];
+  T(*my)[NF][kWave] = ring[w];
   // Output staging: the block's WPB * 60 new values of a row are gathered
   // in LDS (double buffered) and written back as whole 128-byte lines
   // starting at the block's first column, a multiple of 15 lines.
   constexpr int BW = WPB * kTileW;
-  __shared__ T obuf[2][4][BW];
+  __shared__ T obuf[2][NF][BW];
   const int xb = bx * BW;   // first column of the block
   const int kst = w * kWave + lane;  // column (in the block) this lane stores
   int par = 0;
-  auto ring_put = [&](int row, const T (&q)[4]) {
+  auto ring_put = [&](int row, const T (&q)[NF]) {
     const int sl = row % 3;
-    my[sl][0][lane] = q[0];
-    my[sl][1][lane] = q[1];
-    my[sl][2][lane] = q[2];
-    my[sl][3][lane] = q[3];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) my[sl][f][lane] = q[f];
+  };
+  // mass fractions y_k = (rho y_k) / rho of a loaded row
+  auto fractions = [&](const T (&q)[NF]) {
+    Frac<T, NS> y;
+    if constexpr (NS > 0) {
+      const T ir = rcp(q[0]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) y.v[s] = q[4 + s] * ir;
+    }
+    return y;
   };
 
-  T QA[4], QB[4], BA[4] = {T(0), T(0), T(0), T(0)}, BB[4] = {T(0), T(0), T(0), T(0)};
+  T QA[NF], QB[NF], BA[NF], BB[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) BA[f] = BB[f] = T(0);
   Prim<T> W0, W1, Sg0, Sg1;
   Flux<T> Gf0, Gf1;
+  // the same window for the mass fractions: values, y-slopes and the flux
+  // through the last y-face
+  Frac<T, NS> Y0, Y1, Sy0, Sy1, Gy0, Gy1;
   {
-    T qa[4], qb[4], q0[4], q1[4];
+    T qa[NF], qb[NF], q0[NF], q1[NF];
     load_row(y0 - 2, qa);
     load_row(y0 - 1, qb);
     load_row(y0, q0);
@@ -172,17 +206,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     load_row(y0 + 3, QB);
     if constexpr (MODE == kCorrector) {
       const int o0 = y0 * nx + cm;
-      BA[0] = B0[o0];
-      BA[1] = B1[o0];
-      BA[2] = B2[o0];
-      BA[3] = B3[o0];
-      if (y0 + 1 < y1) {
-        const int o1 = o0 + nx;
-        BB[0] = B0[o1];
-        BB[1] = B1[o1];
-        BB[2] = B2[o1];
-        BB[3] = B3[o1];
-      }
+      load_base(o0, BA);
+      if (y0 + 1 < y1) load_base(o0 + nx, BB);
     }
     Prim<T> wa = to_prim(qa[0], qa[1], qa[2], qa[3], gm1);
     Prim<T> wb = to_prim(qb[0], qb[1], qb[2], qb[3], gm1);
@@ -194,7 +219,19 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     Prim<T> d_mid = sub(W0, wb);   // y0 - 1/2
     Prim<T> s_b = slope(d_lo, d_mid, beta);
     Sg0 = slope(d_mid, sub(W1, W0), beta);
-    Gf0 = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(W0, Sg0), gam, igm1);
+    bool gl;
+    Gf0 = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(W0, Sg0), gam, igm1, gl);
+    if constexpr (NS > 0) {
+      const Frac<T, NS> ya = fractions(qa), yb = fractions(qb);
+      Y0 = fractions(q0);
+      Y1 = fractions(q1);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const T sb = sweby(yb.v[s] - ya.v[s], Y0.v[s] - yb.v[s], beta);
+        Sy0.v[s] = sweby(Y0.v[s] - yb.v[s], Y1.v[s] - Y0.v[s], beta);
+        Gy0.v[s] = Gf0.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? sb : Sy0.v[s], gl ? yb.v[s] : Y0.v[s]);
+      }
+    }
   }
 
   double smax = 0.0;
@@ -203,18 +240,22 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
   // Row o: qc holds row o+2 (arrived) and then receives row o+4; bc holds
   // U^n of row o and then receives row o+2; wo/wo1 are the primitive rows
   // o and o+1 (wo is overwritten with row o+2); so/so1 the y-slopes of rows
-  // o and o+1; Gp/G the fluxes through the y-faces o-1/2 and o+1/2.
-  auto row = [&](int o, T (&qc)[4], T (&bc)[4], Prim<T>& wo, const Prim<T>& wo1, const Prim<T>& so,
-                 Prim<T>& so1, const Flux<T>& Gp, Flux<T>& G) {
+  // o and o+1; Gp/G the fluxes through the y-faces o-1/2 and o+1/2.  The
+  // mass fractions rotate the same way (yo, yo1, syo, syo1, gyp, gy).
+  auto row = [&](int o, T (&qc)[NF], T (&bc)[NF], Prim<T>& wo, const Prim<T>& wo1, const Prim<T>& so,
+                 Prim<T>& so1, const Flux<T>& Gp, Flux<T>& G, Frac<T, NS>& yo, const Frac<T, NS>& yo1,
+                 const Frac<T, NS>& syo, Frac<T, NS>& syo1, const Frac<T, NS>& gyp, Frac<T, NS>& gy) {
     const int off = o * nx + cm;
     const Prim<T> wn = to_prim(qc[0], qc[1], qc[2], qc[3], gm1);
+    const Frac<T, NS> yn = fractions(qc);
     ring_put(o + 2, qc);
     if (o + 3 <= y1) load_row(o + 4, qc);
 
     // y: slope of row o+1, flux through face o+1/2
     const Prim<T> dlo = sub(wo1, wo);
     so1 = slope(dlo, sub(wn, wo1), beta);
-    G = face_flux(face_plus<T, true>(wo, so), face_minus<T, true>(wo1, so1), gam, igm1);
+    bool gl;
+    G = face_flux(face_plus<T, true>(wo, so), face_minus<T, true>(wo1, so1), gam, igm1, gl);
 
     // x: slopes of row o from lane neighbours, flux through face c+1/2
     const Prim<T> wr1 = shl1(wo);       // w_{c+1}
@@ -222,7 +263,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const Prim<T> dxm = shr1(dxp);      // w_c - w_{c-1}
     const Prim<T> sx = slope(dxm, dxp, beta);
     const Prim<T> sx1 = shl1(sx);       // sigma_{c+1}
-    const Flux<T> F = face_flux(face_plus<T, false>(wo, sx), face_minus<T, false>(wr1, sx1), gam, igm1);
+    bool fl;
+    const Flux<T> F = face_flux(face_plus<T, false>(wo, sx), face_minus<T, false>(wr1, sx1), gam, igm1, fl);
     const Flux<T> Fm = shr1(F);         // flux through face c-1/2
 
     // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11),
@@ -233,19 +275,36 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const T r2 = fma(G.f1 - Gp.f1, a.kxy, F.f2 - Fm.f2) * a.idx;
     const T r3 = fma(G.f3 - Gp.f3, a.kxy, F.f3 - Fm.f3) * a.idx;
 
+    // Mass fractions: reconstructed like the primitive variables and
+    // carried by the face mass flux from its upwind side, (rho_A u*) y_A.
+    // The upwind face value is one fma whose operands are selected
+    // (y + s/2 from the left cell or y - s/2 from the right one): written
+    // as a select of two fmas, the compiler may branch on the side and
+    // move the lane shift of the right cell's slope into one arm, where
+    // the lanes of the other arm are inactive and read as zero.
+    T rs[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      syo1.v[s] = sweby(yo1.v[s] - yo.v[s], yn.v[s] - yo1.v[s], beta);
+      gy.v[s] = G.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? syo.v[s] : syo1.v[s], gl ? yo.v[s] : yo1.v[s]);
+      const T yr1 = shl1(yo.v[s]);
+      const T dp = yr1 - yo.v[s];
+      const T sxs = sweby(shr1(dp), dp, beta);
+      const T sxs1 = shl1(sxs);
+      const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? yo.v[s] : yr1);
+      rs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy)) * a.idx;
+    }
+
     const int sl = o % 3;
     const T u0 = combine<MODE>(my[sl][0][lane], bc[0], r0, dt);
     const T u1 = combine<MODE>(my[sl][1][lane], bc[1], r1, dt);
     const T u2 = combine<MODE>(my[sl][2][lane], bc[2], r2, dt);
     const T u3 = combine<MODE>(my[sl][3][lane], bc[3], r3, dt);
+    T us_[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) us_[s] = combine<MODE>(my[sl][4 + s][lane], bc[4 + s], rs[s], dt);
     if constexpr (MODE == kCorrector) {
-      if (o + 2 < y1) {
-        const int o2 = off + 2 * nx;
-        bc[0] = B0[o2];
-        bc[1] = B1[o2];
-        bc[2] = B2[o2];
-        bc[3] = B3[o2];
-      }
+      if (o + 2 < y1) load_base(off + 2 * nx, bc);
     }
     {
       if (out_lane) {
@@ -254,6 +313,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
         obuf[par][1][k] = u1;
         obuf[par][2][k] = u2;
         obuf[par][3][k] = u3;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) obuf[par][4 + s][k] = us_[s];
       }
       __syncthreads();
       const int col = xb + kst;
@@ -263,6 +324,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
         O1[so] = obuf[par][1][kst];
         O2[so] = obuf[par][2][kst];
         O3[so] = obuf[par][3][kst];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) OS[s * plane + so] = obuf[par][4 + s][kst];
       }
       par ^= 1;
     }
@@ -283,11 +346,12 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       }
     }
     wo = wn;  // slot of row o now holds row o+2
+    yo = yn;
   };
 
   for (int o = y0; o < y1; o += 2) {
-    row(o, QA, BA, W0, W1, Sg0, Sg1, Gf0, Gf1);
-    if (o + 1 < y1) row(o + 1, QB, BB, W1, W0, Sg1, Sg0, Gf1, Gf0);
+    row(o, QA, BA, W0, W1, Sg0, Sg1, Gf0, Gf1, Y0, Y1, Sy0, Sy1, Gy0, Gy1);
+    if (o + 1 < y1) row(o + 1, QB, BB, W1, W0, Sg1, Sg0, Gf1, Gf0, Y1, Y0, Sy1, Sy0, Gy1, Gy0);
   }
 
   if constexpr (MODE == kCorrector) {
@@ -405,49 +469,53 @@ __device__ __forceinline__ Acc acc_merge(Acc a, Acc b) {
   return r;
 }
 
+constexpr int kMaxFields = 4 + kMaxSpecies;
+
 template <int NT>
-__device__ void block_merge(Acc (&v)[4], Acc (*sh)[NT]) {
-  for (int f = 0; f < 4; ++f) sh[f][threadIdx.x] = v[f];
+__device__ void block_merge(Acc (&v)[kMaxFields], int nf, Acc (*sh)[NT]) {
+  for (int f = 0; f < nf; ++f) sh[f][threadIdx.x] = v[f];
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
-      for (int f = 0; f < 4; ++f) sh[f][threadIdx.x] = acc_merge(sh[f][threadIdx.x], sh[f][threadIdx.x + w]);
+      for (int f = 0; f < nf; ++f) sh[f][threadIdx.x] = acc_merge(sh[f][threadIdx.x], sh[f][threadIdx.x + w]);
     __syncthreads();
   }
-  for (int f = 0; f < 4; ++f) v[f] = sh[f][0];
+  for (int f = 0; f < nf; ++f) v[f] = sh[f][0];
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void totals_partial_kernel(const T* __restrict__ U, long long plane,
+__global__ __launch_bounds__(256) void totals_partial_kernel(const T* __restrict__ U, long long plane, int nf,
                                                              double* __restrict__ part) {
-  __shared__ Acc sh[4][256];
-  Acc v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  __shared__ Acc sh[kMaxFields][256];
+  Acc v[kMaxFields];
+  for (int f = 0; f < kMaxFields; ++f) v[f] = Acc{0, 0};
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride)
-    for (int f = 0; f < 4; ++f) v[f] = acc_add(v[f], double(U[f * plane + q]));
-  block_merge<256>(v, sh);
+    for (int f = 0; f < nf; ++f) v[f] = acc_add(v[f], double(U[f * plane + q]));
+  block_merge<256>(v, nf, sh);
   if (threadIdx.x == 0)
-    for (int f = 0; f < 4; ++f) {
-      part[(blockIdx.x * 4 + f) * 2 + 0] = v[f].s;
-      part[(blockIdx.x * 4 + f) * 2 + 1] = v[f].c;
+    for (int f = 0; f < nf; ++f) {
+      part[(blockIdx.x * kMaxFields + f) * 2 + 0] = v[f].s;
+      part[(blockIdx.x * kMaxFields + f) * 2 + 1] = v[f].c;
     }
 }
 
-__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ part, int nblk,
+__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ part, int nblk, int nf,
                                                            double area, Ctl* ctl) {
-  __shared__ Acc sh[4][256];
-  Acc v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  __shared__ Acc sh[kMaxFields][256];
+  Acc v[kMaxFields];
+  for (int f = 0; f < kMaxFields; ++f) v[f] = Acc{0, 0};
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-    for (int f = 0; f < 4; ++f)
-      v[f] = acc_merge(v[f], Acc{part[(b * 4 + f) * 2], part[(b * 4 + f) * 2 + 1]});
-  block_merge<256>(v, sh);
+    for (int f = 0; f < nf; ++f)
+      v[f] = acc_merge(v[f], Acc{part[(b * kMaxFields + f) * 2], part[(b * kMaxFields + f) * 2 + 1]});
+  block_merge<256>(v, nf, sh);
   if (threadIdx.x == 0)
-    for (int f = 0; f < 4; ++f) ctl->totals[f] = (v[f].s + v[f].c) * area;
+    for (int f = 0; f < nf; ++f) ctl->totals[f] = (v[f].s + v[f].c) * area;
 }
 
 // ---- host launchers -----------------------------------------------------------
 
-template <typename T, int MODE, int BCX, int BCY>
+template <typename T, int MODE, int BCX, int BCY, int NS>
 static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base, void* out, double dt,
                                  Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
   StageArgs<T> a;
@@ -474,9 +542,22 @@ static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;
-  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY>), dim3(g.blocks_pad), dim3(kWave * waves_per_block<T>()), 0,
-                     s, a);
+  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY, NS>), dim3(g.blocks_pad),
+                     dim3(kWave * waves_per_block<T>()), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int MODE, int BCX, int BCY>
+static hipError_t launch_stage_ns(const Grid& g, const void* in, const void* base, void* out, double dt,
+                                  Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
+  static_assert(kMaxSpecies == 4, "one instantiation per species count");
+  switch (g.ns) {
+    case 0: return launch_stage_t<T, MODE, BCX, BCY, 0>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 1: return launch_stage_t<T, MODE, BCX, BCY, 1>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 2: return launch_stage_t<T, MODE, BCX, BCY, 2>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 3: return launch_stage_t<T, MODE, BCX, BCY, 3>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    default: return launch_stage_t<T, MODE, BCX, BCY, 4>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+  }
 }
 
 template <typename T, int MODE>
@@ -484,12 +565,12 @@ static hipError_t launch_stage_bc(const Grid& g, const void* in, const void* bas
                                   Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
   if (g.bc_x == kBcPeriodic) {
     if (g.bc_y == kBcPeriodic)
-      return launch_stage_t<T, MODE, kBcPeriodic, kBcPeriodic>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
-    return launch_stage_t<T, MODE, kBcPeriodic, kBcTransmissive>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+      return launch_stage_ns<T, MODE, kBcPeriodic, kBcPeriodic>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    return launch_stage_ns<T, MODE, kBcPeriodic, kBcTransmissive>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
   }
   if (g.bc_y == kBcPeriodic)
-    return launch_stage_t<T, MODE, kBcTransmissive, kBcPeriodic>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
-  return launch_stage_t<T, MODE, kBcTransmissive, kBcTransmissive>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    return launch_stage_ns<T, MODE, kBcTransmissive, kBcPeriodic>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+  return launch_stage_ns<T, MODE, kBcTransmissive, kBcTransmissive>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
 }
 
 template <typename T>
@@ -549,11 +630,12 @@ hipError_t launch_totals(const Grid& g, const Layout& L, const void* U, void* ws
   Ctl* ctl = reinterpret_cast<Ctl*>(w + L.ctl);
   if (g.dtype == 0)
     hipLaunchKernelGGL(totals_partial_kernel<double>, dim3(L.totals_blocks), dim3(256), 0, s,
-                       static_cast<const double*>(U), plane, part);
+                       static_cast<const double*>(U), plane, 4 + g.ns, part);
   else
     hipLaunchKernelGGL(totals_partial_kernel<float>, dim3(L.totals_blocks), dim3(256), 0, s,
-                       static_cast<const float*>(U), plane, part);
-  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, s, part, L.totals_blocks, g.dx * g.dy, ctl);
+                       static_cast<const float*>(U), plane, 4 + g.ns, part);
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, s, part, L.totals_blocks, 4 + g.ns,
+                     g.dx * g.dy, ctl);
   return hipGetLastError();
 }
 
@@ -562,8 +644,9 @@ hipError_t launch_totals(const Grid& g, const Layout& L, const void* U, void* ws
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, double beta, int bc_x,
-               int bc_y, int dtype) {
+               int bc_y, int dtype, int ns) {
   Grid g;
+  g.ns = ns;
   g.nx = nx;
   g.ny = ny;
   g.dx = dx;
@@ -601,13 +684,15 @@ Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, d
 Layout make_layout(const Grid& g) {
   Layout L;
   const size_t esz = g.dtype == 0 ? sizeof(double) : sizeof(float);
-  const size_t state = 4 * (size_t)g.nx * (size_t)g.ny * esz;
+  const size_t plane = (size_t)g.nx * (size_t)g.ny * esz;
   L.totals_blocks = reduction_blocks((long long)g.nx * g.ny);
   L.ustar = 0;
-  L.mu = align256(L.ustar + state);
-  L.ctl = align256(L.mu + state);
+  // U* carries every field; the adjoint intermediate only the Euler ones
+  // (the adjoint is defined for states without mass fractions)
+  L.mu = align256(L.ustar + (4 + g.ns) * plane);
+  L.ctl = align256(L.mu + 4 * plane);
   L.partials = align256(L.ctl + sizeof(Ctl));
-  L.total = align256(L.partials + (size_t)L.totals_blocks * 8 * sizeof(double));
+  L.total = align256(L.partials + (size_t)L.totals_blocks * kMaxFields * 2 * sizeof(double));
   return L;
 }
 

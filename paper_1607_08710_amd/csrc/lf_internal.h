@@ -16,6 +16,7 @@ struct Grid {
   double dx, dy, gamma, cfl, beta;
   int bc_x, bc_y;
   int dtype;            // 0 = double, 1 = float
+  int ns;               // passive mass fractions carried after the 4 Euler fields
   int tiles_x, tiles_y; // wave tiles of kTileW columns x rows_per_wave rows
   int rows_per_wave;
   int wpb;              // waves per stage block (a block is wpb adjacent tiles)
@@ -25,7 +26,7 @@ struct Grid {
 
 // Workspace layout (byte offsets from ws, all 256-byte aligned).
 struct Layout {
-  size_t ustar;     // predictor state U* (4 planes of the context dtype)
+  size_t ustar;     // predictor state U* (4 + ns planes of the context dtype)
   size_t mu;        // adjoint intermediate (4 planes)
   size_t ctl;       // Ctl
   size_t partials;  // totals: per-block (sum, compensation) pairs
@@ -34,7 +35,7 @@ struct Layout {
 };
 
 Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, double beta,
-               int bc_x, int bc_y, int dtype);
+               int bc_x, int bc_y, int dtype, int ns);
 Layout make_layout(const Grid& g);
 
 // Stage kernel modes.

@@ -18,7 +18,7 @@ def solver_for(cfg, dtype="f64", **over):
     import paper_1607_08710_amd as L
     kw = dict(nx=cfg["nx"], ny=cfg["ny"], dx=cfg["dx"], dy=cfg["dy"], gamma=cfg["gamma"],
               cfl=cfg["cfl"], beta=cfg["beta"], bc_x=cfg["bc_x"], bc_y=cfg["bc_y"],
-              dtype=L.LF_F64 if dtype == "f64" else L.LF_F32)
+              dtype=L.LF_F64 if dtype == "f64" else L.LF_F32, n_species=cfg.get("ns", 0))
     kw.update(over)
     return L.Solver(L.Params(**kw))
 
@@ -47,7 +47,7 @@ def rel_linf(a, b, floor_fields=(1,)):
     """Per-field max|a-b| / max|b|.  A field that is identically zero in b
     is measured against max|b| of the fields in floor_fields (momentum)."""
     out = []
-    for f in range(4):
+    for f in range(b.shape[0]):
         den = np.abs(b[f]).max()
         if den == 0:
             den = max(np.abs(b[k]).max() for k in floor_fields) or 1.0
@@ -57,7 +57,7 @@ def rel_linf(a, b, floor_fields=(1,)):
 
 def rel_l1(a, b, floor_fields=(1,)):
     out = []
-    for f in range(4):
+    for f in range(b.shape[0]):
         den = np.abs(b[f]).sum()
         if den == 0:
             den = max(np.abs(b[k]).sum() for k in floor_fields) or 1.0
@@ -93,10 +93,11 @@ def sample_patch(U, cfg, i, j, r=4):
 
 def oracle_step_at(U, cfg, dt, cells, r=4):
     """Oracle Heun step evaluated only at the listed cells, from patches."""
-    out = np.empty((len(cells), 4))
+    out = np.empty((len(cells), U.shape[0]))
     for k, (i, j) in enumerate(cells):
         patch, ic, jc = sample_patch(U, cfg, i, j, r)
         P = oracle.Params(patch.shape[2], patch.shape[1], cfg["dx"], cfg["dy"], cfg["gamma"],
-                          cfg["cfl"], cfg["beta"], oracle.TRANSMISSIVE, oracle.TRANSMISSIVE)
+                          cfg["cfl"], cfg["beta"], oracle.TRANSMISSIVE, oracle.TRANSMISSIVE,
+                          ns=U.shape[0] - 4)
         out[k] = oracle.step(P, patch, dt)[:, jc, ic]
     return out

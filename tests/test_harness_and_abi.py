@@ -63,7 +63,7 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(dx=0.0), dict(dy=float("nan")),
                                  dict(gamma=1.0), dict(gamma=3.5), dict(beta=-0.1), dict(beta=2.5), dict(beta=0.5),
                                  dict(cfl=0.0), dict(bc_x=2), dict(bc_y=-1), dict(dtype=7),
-                                 dict(nx=65536, ny=65536)])
+                                 dict(nx=65536, ny=65536), dict(n_species=-1), dict(n_species=5)])
 def test_init_rejects(bad):
     import paper_1607_08710_amd as L
     with pytest.raises(L.LFError) as e:
@@ -112,6 +112,28 @@ def test_entry_points_validate_before_hip():
     assert lib.lf_adjoint_step(ctx, A, 0.1, B, A, W, None) == E
     assert lib.lf_adjoint_step(ctx, A, -0.1, B, vp(0x800000), W, None) == E
     assert lib.lf_totals(ctx, A, W, None, None) == E
+    lib.lf_destroy(ctx)
+
+
+def test_species_context_validation():
+    """With mass fractions the state holds 4 + n_species planes (the
+    overlap checks use that size) and the adjoint entry points refuse the
+    context; all of it is decided before any HIP call."""
+    import paper_1607_08710_amd as L
+    lib = L.lib()
+    ctx0, ws0 = L.init(_params())
+    ctx, ws = L.init(_params(n_species=3))
+    assert ws >= ws0 + 3 * 64 * 32 * 8  # U* carries the fractions too
+    L.lib().lf_destroy(ctx0)
+    vp = ctypes.c_void_p
+    state = 7 * 64 * 32 * 8
+    A, B, C, W = vp(0x1000000), vp(0x2000000), vp(0x3000000), vp(0x10000000)
+    E = L.LF_ERR_ARG
+    # out starts inside the 7-plane input (it would not overlap a 4-plane one)
+    assert lib.lf_step(ctx, A, vp(0x1000000 + 5 * 64 * 32 * 8), 0.1, W, None) == E
+    assert lib.lf_residual(ctx, A, vp(0x1000000 + state - 8), W, None) == E
+    assert lib.lf_residual_vjp(ctx, A, B, C, W, None) == E
+    assert lib.lf_adjoint_step(ctx, A, 0.1, B, C, W, None) == E
     lib.lf_destroy(ctx)
 
 
