@@ -55,7 +55,7 @@ def kernel_source_hash() -> str:
 
 def make_solver(L, cfg, dtype):
     return L.Solver(L.Params(cfg["nx"], cfg["ny"], cfg["dx"], cfg["dy"], cfg["gamma"], cfg["cfl"],
-                             cfg["beta"], cfg["bc_x"], cfg["bc_y"], dtype))
+                             cfg["beta"], cfg["bc_x"], cfg["bc_y"], dtype, cfg.get("ns", 0)))
 
 
 def time_advance(S, U, steps, warmup):
@@ -98,11 +98,11 @@ def time_stages(S, U, reps):
     return pred / 1e3, corr / 1e3
 
 
-def forward_leg(L, W, n, dtype_flag, steps, warmup, reps):
+def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0):
     import torch
     tdt = torch.float64 if dtype_flag == L.LF_F64 else torch.float32
     esz = 8 if dtype_flag == L.LF_F64 else 4
-    U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt)
+    U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=fractions)
     S = make_solver(L, cfg, dtype_flag)
     tot0 = S.totals(U)
     sec, wall = time_advance(S, U, steps, warmup)
@@ -111,14 +111,18 @@ def forward_leg(L, W, n, dtype_flag, steps, warmup, reps):
     cups = cells * steps / sec
     pred, corr = time_stages(S, U, reps)
     drift = [float(b - a) for a, b in zip(tot0, tot1)]
+    # algorithmic bytes scale with the number of fields (4 Euler + fractions)
+    fw = (4 + fractions) / 4
     res = {
         "value": cups, "ms_per_step": 1e3 * sec / steps, "wall_s": wall,
-        "step_effective_GBps": BYTES_PER_CELL[("step", esz)] * cells * steps / sec / 1e9,
+        "step_effective_GBps": fw * BYTES_PER_CELL[("step", esz)] * cells * steps / sec / 1e9,
         "predictor_ms": 1e3 * pred, "corrector_ms": 1e3 * corr,
-        "predictor_GBps": BYTES_PER_CELL[("predictor", esz)] * cells / pred / 1e9,
-        "corrector_GBps": BYTES_PER_CELL[("corrector", esz)] * cells / corr / 1e9,
+        "predictor_GBps": fw * BYTES_PER_CELL[("predictor", esz)] * cells / pred / 1e9,
+        "corrector_GBps": fw * BYTES_PER_CELL[("corrector", esz)] * cells / corr / 1e9,
         "totals_initial": [float(a) for a in tot0], "totals_drift": drift,
     }
+    if fractions:
+        res["fractions"] = fractions
     del U, S
     torch.cuda.empty_cache()
     return res
@@ -245,9 +249,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="forward,adjoint,cpu",
-                    help="comma list of legs to run: forward, adjoint, cpu (profiling runs use one leg "
-                         "so that each kernel runs at one grid size)")
+    ap.add_argument("--legs", default="forward,species,adjoint,cpu",
+                    help="comma list of legs to run: forward, species, adjoint, cpu (profiling runs use "
+                         "one leg so that each kernel runs at one grid size)")
+    ap.add_argument("--species-steps", type=int, default=200)
     ap.add_argument("--profile-pass", choices=["none", "kernels"], default="none")
     args = ap.parse_args()
 
@@ -274,6 +279,7 @@ def main():
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
     f64 = f32 = adj64 = adj32 = roofline = cpu = None
+    species = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
         f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
@@ -291,6 +297,14 @@ def main():
                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "traffic_source": traffic_src,
                     "algorithmic_bytes_per_cell": BYTES_PER_CELL[("corrector", 8)], "cells_per_launch": cells,
                     "avg_launch_ms": f64["corrector_ms"]}
+    if "species" in legs:
+        species = {}
+        for k in (1, 2):
+            log(f"FP64 Kelvin-Helmholtz {args.n}^2 with {k} mass fraction(s): {args.species_steps} steps")
+            r = forward_leg(L, W, args.n, L.LF_F64, args.species_steps, args.warmup, args.kernel_reps,
+                            fractions=k)
+            species[f"f64_ns{k}"] = r
+            log(f"  {r['value'] / 1e9:.2f} G cell-updates/s, corrector {r['corrector_GBps']:.0f} GB/s")
     if "adjoint" in legs:
         log(f"adjoint {args.adj_n}^2, {args.adj_steps} steps, checkpoints every {args.adj_ckpt}")
         adj64 = adjoint_leg(L, W, args.adj_n, L.LF_F64, args.adj_steps, args.adj_ckpt, 10)
@@ -323,6 +337,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64": f64,
         "fp32": f32,
+        "species": species,
         "adjoint": {"n": args.adj_n, "steps": args.adj_steps, "ckpt_every": args.adj_ckpt,
                     "f64": adj64, "f32": adj32},
         "paper_context": {"value": 81.0e6, "unit": "cell-updates/s",

@@ -225,10 +225,12 @@ def random_state(nx: int, ny: int, seed: int, *, gamma: float = 1.4, rough: bool
     return prim_to_cons(gamma, rho, u, v, p)
 
 
-def kelvin_helmholtz_torch(n: int, *, device="cuda", dtype=None, gamma: float = 1.4):
+def kelvin_helmholtz_torch(n: int, *, device="cuda", dtype=None, gamma: float = 1.4, fractions: int = 0):
     """The Kelvin-Helmholtz state of kelvin_helmholtz(), built with torch
     directly in device memory (for the large benchmark grids).  Computed in
-    float64 and cast once to ``dtype``."""
+    float64 and cast once to ``dtype``.  With ``fractions`` = K > 0 the
+    state also carries K mass fractions: the band marker of
+    kelvin_helmholtz_fraction() first, then (1 + sin(2 pi (k+1) x)) / 2."""
     import torch
     dtype = dtype or torch.float64
     x = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) / n
@@ -236,7 +238,7 @@ def kelvin_helmholtz_torch(n: int, *, device="cuda", dtype=None, gamma: float = 
     rho_y = torch.where(inner, 2.0, 1.0)
     u_y = torch.where(inner, 0.5, -0.5)
     v_x = 0.01 * torch.sin(4.0 * math.pi * x)
-    U = torch.empty((4, n, n), dtype=dtype, device=device)
+    U = torch.empty((4 + fractions, n, n), dtype=dtype, device=device)
     rho = rho_y[:, None].expand(n, n)
     u = u_y[:, None].expand(n, n)
     v = v_x[None, :].expand(n, n)
@@ -244,7 +246,15 @@ def kelvin_helmholtz_torch(n: int, *, device="cuda", dtype=None, gamma: float = 
     U[1] = rho * u
     U[2] = rho * v
     U[3] = 2.5 / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    for k in range(fractions):
+        if k == 0:
+            y = inner.to(torch.float64)[:, None].expand(n, n)
+        else:
+            y = (0.5 * (1.0 + torch.sin(2.0 * math.pi * (k + 1) * x)))[None, :].expand(n, n)
+        U[4 + k] = rho * y
     cfg = _cfg(n, n, 1.0, 1.0, PERIODIC, PERIODIC, gamma, 0.5, 1.5, steps=500)
+    if fractions:
+        cfg["ns"] = fractions
     return U, cfg
 
 
