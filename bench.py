@@ -209,10 +209,11 @@ def traffic_entry(n):
 
 def profile_pass(L, W, n):
     """Fixed short sequence for rocprofv3: each stage kernel of both
-    precisions a few times, then a plain device copy of known size."""
+    precisions (and the FP64 one with one mass fraction) a few times, then
+    a plain device copy of known size."""
     import torch
-    for flag, tdt in ((L.LF_F64, torch.float64), (L.LF_F32, torch.float32)):
-        U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt)
+    for flag, tdt, k in ((L.LF_F64, torch.float64, 0), (L.LF_F32, torch.float32, 0), (L.LF_F64, torch.float64, 1)):
+        U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=k)
         S = make_solver(L, cfg, flag)
         S.advance(U, 0.0, math.inf, max_steps=3)
         time_stages(S, U, 5)
