@@ -4,14 +4,17 @@
 Workload: the periodic Kelvin-Helmholtz shear layer at 16384^2 cells (rho 2
 with u = 0.5 inside |y - 1/2| < 1/4, rho 1 with u = -0.5 outside, p = 2.5,
 v = 0.01 sin(4 pi x)), synthetic inputs built on the device.  A step is one
-full Heun step of the scheme: predictor stage, corrector stage with the
-fused CFL reduction, and the device-side dt update, all through lf_advance.
+full Heun step of the scheme (predictor, corrector, the CFL reduction of
+the new state and the device-side dt update) through lf_advance, which runs
+it as one single-pass kernel per step.
 
-Prints ONE JSON line on stdout: the FP64 cell-updates/s as ``value``, the
-FP32 path and the adjoint (lf_adjoint_step and the checkpointed full
-gradient at 4096^2) as extra objects, the HBM roofline of the dominant
-kernel (the FP64 corrector stage) measured with HIP events on the stream it
-runs on, and the FP64 CPU oracle timed on a bounded sample on this host.
+Prints ONE JSON line on stdout: the FP64 cell-updates/s as ``value``; the
+roofline of the dominant kernel (the single-pass step, bound by VALU issue)
+and of the two-stage design's corrector against HBM, each from HIP events
+on the stream the kernel runs on; the FP32 path, the two-stage path, the
+mass-fraction runs and the adjoint (lf_adjoint_step and the checkpointed
+full gradient at 4096^2) as extra objects; and the FP64 CPU oracle timed on
+a bounded sample on this host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --profile-pass kernels   # short fixed sequence for rocprofv3
@@ -30,13 +33,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
+# (FP64 add/mul/fma, FP32 unpacked, DPP moves and selects all issue at this
+# rate; FP64 vector FMA peak 78.6 TFLOP/s = 2 x this)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BYTES_PER_CELL = {               # algorithmic (compulsory) bytes per cell
     ("corrector", 8): 96, ("predictor", 8): 64, ("step", 8): 160,
     ("corrector", 4): 48, ("predictor", 4): 32, ("step", 4): 80,
+    ("single_pass", 8): 64, ("single_pass", 4): 32,
     ("adjoint_step", 8): 288, ("adjoint_step", 4): 144,
 }
-KERNEL_SOURCES = ["paper_1607_08710_amd/csrc/lf_forward.hip", "paper_1607_08710_amd/csrc/lf_device.h",
-                  "paper_1607_08710_amd/csrc/lf_internal.h"]
+# VALU instructions per cell and step of the single-pass kernel: one
+# iteration of its main loop (a predictor row, a corrector row and the CFL
+# reduction, per lane) in the gfx950 assembly of fused_step_kernel<T,
+# periodic, periodic>; tests/test_valu_count.py recounts it from a fresh
+# build.
+VALU_OPS_PER_CELL = {8: 679, 4: 576}
+KERNEL_SOURCES = ["paper_1607_08710_amd/csrc/lf_forward.hip", "paper_1607_08710_amd/csrc/lf_fused.hip",
+                  "paper_1607_08710_amd/csrc/lf_device.h", "paper_1607_08710_amd/csrc/lf_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kh16384.json")
 METRIC = "cell-updates/s per step (FP64 vs FP32, % HBM roofline) + adjoint step/s at 4096^2"
 
@@ -98,6 +112,24 @@ def time_stages(S, U, reps):
     return pred / 1e3, corr / 1e3
 
 
+def time_single_pass(S, U, reps):
+    """Average duration of the single-pass step kernel (lf_step into a
+    separate buffer), each launch bracketed by HIP events on the stream the
+    library launches on."""
+    import torch
+    dt = S.dt(U)
+    out = S.empty_state()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        S.step(U, out, dt)
+        b.record()
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / reps
+    del out
+    return ms / 1e3
+
+
 def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0):
     import torch
     tdt = torch.float64 if dtype_flag == L.LF_F64 else torch.float32
@@ -115,14 +147,26 @@ def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0):
     fw = (4 + fractions) / 4
     res = {
         "value": cups, "ms_per_step": 1e3 * sec / steps, "wall_s": wall,
-        "step_effective_GBps": fw * BYTES_PER_CELL[("step", esz)] * cells * steps / sec / 1e9,
         "predictor_ms": 1e3 * pred, "corrector_ms": 1e3 * corr,
         "predictor_GBps": fw * BYTES_PER_CELL[("predictor", esz)] * cells / pred / 1e9,
         "corrector_GBps": fw * BYTES_PER_CELL[("corrector", esz)] * cells / corr / 1e9,
         "totals_initial": [float(a) for a in tot0], "totals_drift": drift,
     }
     if fractions:
+        # lf_advance runs the two stages when the state carries fractions
         res["fractions"] = fractions
+        res["path"] = "two-stage (predictor and corrector kernels, U* through HBM)"
+        res["step_effective_GBps"] = fw * BYTES_PER_CELL[("step", esz)] * cells * steps / sec / 1e9
+    else:
+        sp = time_single_pass(S, U, reps)
+        res["path"] = "single pass (one kernel per step, U* on chip)"
+        res["single_pass_kernel_ms"] = 1e3 * sp
+        # per-step time of the timed lf_advance region: one single-pass launch
+        # (with the CFL reduction) and the dt-update kernel
+        res["single_pass_GBps"] = BYTES_PER_CELL[("single_pass", esz)] * cells * steps / sec / 1e9
+        res["single_pass_valu_TOPs"] = VALU_OPS_PER_CELL[esz] * cells * steps / sec / 1e12
+        res["two_stage"] = {"value": cells / (pred + corr), "step_ms": 1e3 * (pred + corr),
+                            "step_effective_GBps": BYTES_PER_CELL[("step", esz)] * cells / (pred + corr) / 1e9}
     del U, S
     torch.cuda.empty_cache()
     return res
@@ -193,9 +237,10 @@ def cpu_baseline(W, n=2048, min_seconds=10.0, max_steps=400):
                       f"OMP_NUM_THREADS={cores}"}
 
 
-def traffic_entry(n):
-    """HBM bytes per corrector launch from the committed rocprofv3 counter
-    summary, or None when absent or taken from other kernel sources."""
+def traffic_entry(n, key):
+    """HBM bytes per launch of one kernel (key in the counter record, e.g.
+    corrector_f64_bytes) from the committed rocprofv3 counter summary, or
+    None when absent or taken from other kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     with open(TRAFFIC_FILE) as fh:
@@ -204,7 +249,7 @@ def traffic_entry(n):
         return None, "kernel changed since the counters were taken"
     if rec.get("n") != n:
         return None, "counters taken at another size"
-    return rec.get("corrector_f64_bytes"), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel"
+    return rec.get(key), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel"
 
 
 def profile_pass(L, W, n):
@@ -215,8 +260,10 @@ def profile_pass(L, W, n):
     for flag, tdt, k in ((L.LF_F64, torch.float64, 0), (L.LF_F32, torch.float32, 0), (L.LF_F64, torch.float64, 1)):
         U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=k)
         S = make_solver(L, cfg, flag)
-        S.advance(U, 0.0, math.inf, max_steps=3)
+        S.advance(U, 0.0, math.inf, max_steps=4)  # even: no copy back from the workspace
         time_stages(S, U, 5)
+        if k == 0:
+            time_single_pass(S, U, 5)
         torch.cuda.synchronize()
         del U, S
         torch.cuda.empty_cache()
@@ -280,7 +327,7 @@ def main():
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
     f64 = f32 = adj64 = adj32 = roofline = cpu = None
-    species = None
+    species = roofline_two_stage = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
         f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
@@ -288,16 +335,32 @@ def main():
         log(f"FP32 Kelvin-Helmholtz {args.n}^2")
         f32 = forward_leg(L, W, args.n, L.LF_F32, args.steps, args.warmup, args.kernel_reps)
         f32["ratio_vs_fp64"] = f32["value"] / f64["value"]
+        f32["two_stage"]["ratio_vs_fp64"] = f32["two_stage"]["value"] / f64["two_stage"]["value"]
         log(f"FP32 {f32['value'] / 1e9:.2f} G cell-updates/s, {f32['ms_per_step']:.3f} ms/step")
         cells = args.n * args.n
+        # the timed steps run the single-pass kernel: bound by VALU issue; its
+        # launch time is the per-step time of the timed region (which also
+        # holds the few-microsecond dt-update kernel)
+        sp_s = f64["ms_per_step"] / 1e3
+        achieved = VALU_OPS_PER_CELL[8] * cells / sp_s / 1e12
+        traffic, traffic_src = traffic_entry(args.n, "single_pass_f64_bytes")
+        roofline = {"bound": "alu", "kernel": "lf::fused_step_kernel<double, 0, 0> (FP64 single-pass step, periodic)",
+                    "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                    "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_source": traffic_src,
+                    "algorithmic_ops_per_cell": VALU_OPS_PER_CELL[8],
+                    "ops": "VALU lane-instructions per cell-step, counted from the kernel's gfx950 assembly",
+                    "algorithmic_bytes_per_cell": BYTES_PER_CELL[("single_pass", 8)],
+                    "hbm_GBps": BYTES_PER_CELL[("single_pass", 8)] * cells / sp_s / 1e9,
+                    "cells_per_launch": cells, "avg_launch_ms": f64["ms_per_step"]}
+        # the two-stage design (one kernel per stage) against HBM
         corr_s = f64["corrector_ms"] / 1e3
-        achieved = BYTES_PER_CELL[("corrector", 8)] * cells / corr_s / 1e9
-        traffic, traffic_src = traffic_entry(args.n)
-        roofline = {"bound": "hbm", "kernel": "lf::stage_kernel<double, 2, 0, 0> (FP64 corrector, periodic)",
-                    "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "traffic_source": traffic_src,
-                    "algorithmic_bytes_per_cell": BYTES_PER_CELL[("corrector", 8)], "cells_per_launch": cells,
-                    "avg_launch_ms": f64["corrector_ms"]}
+        ach2 = BYTES_PER_CELL[("corrector", 8)] * cells / corr_s / 1e9
+        traffic2, traffic_src2 = traffic_entry(args.n, "corrector_f64_bytes")
+        roofline_two_stage = {"bound": "hbm", "kernel": "lf::stage_kernel<double, 2, 0, 0, 0> (FP64 corrector, periodic)",
+                              "achieved": ach2, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                              "frac": ach2 / HBM_PEAK_GBPS, "traffic": traffic2, "traffic_source": traffic_src2,
+                              "algorithmic_bytes_per_cell": BYTES_PER_CELL[("corrector", 8)],
+                              "cells_per_launch": cells, "avg_launch_ms": f64["corrector_ms"]}
     if "species" in legs:
         species = {}
         for k in (1, 2):
@@ -335,6 +398,7 @@ def main():
                                f"CFL 0.5, Sweby beta 1.5, Heun steps via lf_advance",
                    "nx": args.n, "ny": args.n, "parallelism": "single GPU"},
         "roofline": roofline,
+        "roofline_two_stage": roofline_two_stage,
         "cpu_baseline": cpu,
         "fp64": f64,
         "fp32": f32,

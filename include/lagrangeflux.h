@@ -105,7 +105,10 @@ int lf_dt(lf_ctx *ctx, const void *U, void *ws, void *stream, double *dt_out);
  * flux balance of eq. (11).  Unp1 may equal Un (in-place update); any other
  * overlap is LF_ERR_ARG.  dt must be finite and >= 0.  In the FP32 context
  * the states are float, the flux arithmetic is float and every stage
- * update is formed in FP64 and rounded once. */
+ * update is formed in FP64 and rounded once.  With Unp1 != Un and no mass
+ * fractions the step is one single-pass kernel (U* never leaves the chip);
+ * otherwise U* goes through the workspace.  Either way the result is
+ * bitwise that of lf_stage(1) followed by lf_stage(2). */
 int lf_step(lf_ctx *ctx, const void *Un, void *Unp1, double dt, void *ws, void *stream);
 
 /* One stage of the Heun step at the caller's dt, async (the two kernels
@@ -125,7 +128,10 @@ int lf_stage(lf_ctx *ctx, int stage, const void *in, const void *base, void *out
  * count, and (if dts_out != NULL) the dt of the first min(steps,
  * dts_capacity) steps into the host array dts_out.  Returns
  * LF_ERR_NONPHYSICAL if the initial state or any state produced is
- * non-physical (the state of that step is left in U). */
+ * non-physical (the state of that step is left in U).  Without mass
+ * fractions every step is the single-pass kernel of lf_step, alternating
+ * between U and the workspace's U* buffer; an odd step count ends with one
+ * device copy back into U. */
 int lf_advance(lf_ctx *ctx, void *U, double t0, double t_end, int64_t max_steps,
                void *ws, void *stream, double *t_out, int64_t *steps_out,
                double *dts_out, int64_t dts_capacity);

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SO = os.path.join(PKG, "liblagrangeflux.so")
-SOURCES = ["lf_api.hip", "lf_forward.hip", "lf_adjoint.hip"]
+SOURCES = ["lf_api.hip", "lf_forward.hip", "lf_fused.hip", "lf_adjoint.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -35,59 +35,6 @@ struct StageArgs {
   int reduce;
 };
 
-template <typename T>
-__device__ __forceinline__ Prim<T> sub(const Prim<T>& a, const Prim<T>& b) {
-  return {a.r - b.r, a.u - b.u, a.v - b.v, a.p - b.p};
-}
-
-template <typename T>
-__device__ __forceinline__ Prim<T> slope(const Prim<T>& dm, const Prim<T>& dp, T beta) {
-  return {sweby(dm.r, dp.r, beta), sweby(dm.u, dp.u, beta), sweby(dm.v, dp.v, beta),
-          sweby(dm.p, dp.p, beta)};
-}
-
-// w + s/2 in the x-face frame (u normal) or the y-face frame (v normal).
-template <typename T, bool YFACE>
-__device__ __forceinline__ FaceState<T> face_plus(const Prim<T>& w, const Prim<T>& s) {
-  T h = T(0.5);
-  T r = fma(h, s.r, w.r), u = fma(h, s.u, w.u), v = fma(h, s.v, w.v), p = fma(h, s.p, w.p);
-  if constexpr (YFACE) return {r, v, u, p};
-  else return {r, u, v, p};
-}
-template <typename T, bool YFACE>
-__device__ __forceinline__ FaceState<T> face_minus(const Prim<T>& w, const Prim<T>& s) {
-  T h = T(-0.5);
-  T r = fma(h, s.r, w.r), u = fma(h, s.u, w.u), v = fma(h, s.v, w.v), p = fma(h, s.p, w.p);
-  if constexpr (YFACE) return {r, v, u, p};
-  else return {r, u, v, p};
-}
-
-template <typename T>
-__device__ __forceinline__ Prim<T> shl1(const Prim<T>& w) {
-  return {shl1(w.r), shl1(w.u), shl1(w.v), shl1(w.p)};
-}
-template <typename T>
-__device__ __forceinline__ Prim<T> shr1(const Prim<T>& w) {
-  return {shr1(w.r), shr1(w.u), shr1(w.v), shr1(w.p)};
-}
-template <typename T>
-__device__ __forceinline__ Flux<T> shr1(const Flux<T>& f) {
-  return {shr1(f.f0), shr1(f.f1), shr1(f.f2), shr1(f.f3)};
-}
-
-// Combination of one stage in FP64: predictor U - dt R; corrector
-// (U^n + U* - dt R(U*)) / 2; residual mode writes R.
-template <int MODE, typename T>
-__device__ __forceinline__ T combine(T q, T b, T res, double dt) {
-  if constexpr (MODE == kResidual) {
-    return res;
-  } else if constexpr (MODE == kPredictor) {
-    return T(double(q) - dt * double(res));
-  } else {
-    return T(0.5 * (double(b) + (double(q) - dt * double(res))));
-  }
-}
-
 // Mass fractions of one row (NS of them; one unused slot when NS = 0).
 template <typename T, int NS>
 struct Frac {

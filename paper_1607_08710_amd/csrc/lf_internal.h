@@ -38,14 +38,16 @@ Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, d
                int bc_x, int bc_y, int dtype, int ns);
 Layout make_layout(const Grid& g);
 
-// Stage kernel modes.
-enum StageMode : int { kResidual = 0, kPredictor = 1, kCorrector = 2 };
 
 // in: stencil input; base: U^n for the corrector (may equal out); out.
 // dt_dev != nullptr: read dt from the control block and honour its done flag.
 // reduce: corrector only, reduce the wave speed of the output into ctl.
 hipError_t launch_stage(const Grid& g, int mode, const void* in, const void* base, void* out,
                         double dt, Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s);
+// One whole Heun step in a single pass, out = step(in); in and out must
+// not overlap; states without mass fractions only.
+hipError_t launch_fused_step(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
+                             bool reduce, hipStream_t s);
 hipError_t launch_wavespeed(const Grid& g, const void* U, Ctl* ctl, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, double t0, double t_end, long long max_steps, double cfl,
                            hipStream_t s);

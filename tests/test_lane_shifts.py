@@ -48,7 +48,7 @@ def _shifts_in_divergent_code(asm):
     return found
 
 
-@pytest.mark.parametrize("src", ["lf_forward.hip", "lf_adjoint.hip"])
+@pytest.mark.parametrize("src", ["lf_forward.hip", "lf_fused.hip", "lf_adjoint.hip"])
 def test_no_lane_shift_in_divergent_code(src, tmp_path):
     if not os.path.exists("/opt/rocm/bin/hipcc"):
         pytest.skip("hipcc not installed")

@@ -1,0 +1,55 @@
+"""The single-pass step kernel is bound by VALU issue, and bench.py prices
+it with the number of VALU instructions one iteration of its main loop
+(a predictor row and a corrector row with the CFL reduction, per lane =
+per cell) takes in the gfx950 assembly.  This test recounts that number from a fresh compile, so
+the figure the benchmark reports cannot drift from the kernel."""
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1607_08710_amd", "csrc")
+
+
+def _main_loop_valu(asm, symbol):
+    start = asm.index(symbol + ":")
+    end = asm.index(".Lfunc_end", start)
+    lines = [l.strip() for l in asm[start:end].split("\n")]
+    labels = {}
+    for i, l in enumerate(lines):
+        m = re.match(r"^(\.LBB\S+):", l)
+        if m:
+            labels[m.group(1)] = i
+    loops = []
+    for i, l in enumerate(lines):
+        m = re.search(r"s_c?branch\w*\s+(\.LBB\S+)", l)
+        if m and m.group(1) in labels and labels[m.group(1)] < i:
+            loops.append((labels[m.group(1)], i))
+    # The main loop stores the new state.  It is rotated: one back edge
+    # skips the CFL reduction block (lf_step), the other runs through it
+    # (lf_advance, the timed path); the iteration counted is the latter,
+    # the longest loop that stores.
+    body = [lines[a:b + 1] for a, b in loops if any(x.startswith("global_store") for x in lines[a:b + 1])]
+    assert body, loops
+    body = max(body, key=len)
+    assert any(x.startswith("v_rsq") for x in body)  # the reduction's sound speed is in it
+    return sum(1 for x in body if x.startswith("v_"))
+
+
+def test_single_pass_valu_count(tmp_path):
+    if not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc not installed")
+    from paper_1607_08710_amd import _build
+    sys.path.insert(0, ROOT)
+    import bench
+    out = str(tmp_path / "fused.s")
+    flags = [f for f in _build.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    subprocess.run([_build.hipcc(), *flags, "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
+                    "-I", CSRC, "-o", out, os.path.join(CSRC, "lf_fused.hip")], check=True, capture_output=True)
+    asm = open(out).read()
+    got = {8: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIdLi0ELi0EEEvNS_9FusedArgsIT_EE"),
+           4: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIfLi0ELi0EEEvNS_9FusedArgsIT_EE")}
+    assert got == bench.VALU_OPS_PER_CELL, got
