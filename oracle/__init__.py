@@ -30,6 +30,9 @@ _SO = os.path.join(_HERE, "liblfo.so")
 PERIODIC = 0
 TRANSMISSIVE = 1
 
+RECON_PRIMITIVE = 0
+RECON_CONSERVATIVE = 1
+
 OK = 0
 ERR_ARG = 1
 ERR_NONPHYSICAL = 3
@@ -54,7 +57,7 @@ class _Params(ctypes.Structure):
         ("dx", ctypes.c_double), ("dy", ctypes.c_double),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("beta", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
-        ("ns", ctypes.c_int32),
+        ("ns", ctypes.c_int32), ("recon", ctypes.c_int32),
     ]
 
 
@@ -70,10 +73,11 @@ class Params:
     bc_x: int = PERIODIC
     bc_y: int = PERIODIC
     ns: int = 0  # passive mass fractions: fields 4 .. 3+ns hold rho*y_k
+    recon: int = 0  # RECON_PRIMITIVE (Sec. 5) or RECON_CONSERVATIVE (ablation)
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.dx, self.dy, self.gamma, self.cfl,
-                       self.beta, self.bc_x, self.bc_y, self.ns)
+                       self.beta, self.bc_x, self.bc_y, self.ns, self.recon)
 
     def with_(self, **kw) -> "Params":
         d = dict(self.__dict__)

@@ -223,6 +223,50 @@ static void stencil_face(double gamma, double beta, const double W[4][4],
     }
 }
 
+/* The conservative-variable reconstruction (an alternative to the primitive
+ * one of Sec. 5): Q[k] = face-frame conservative state (rho, rho u_n,
+ * rho u_t, rho E) of cells m-1 .. m+2; the limited slopes of eq. (sweby)
+ * act on Q, the two face states are converted to primitive variables for
+ * the acoustic solve of eqs. (13)-(14), and eq. (12) takes the
+ * reconstructed conservative vector of the upwind side. */
+static void stencil_face_cons(double gamma, double beta, const double Q[4][4], double phi[4])
+{
+    double ql[4], qr[4], wl[4], wr[4];
+    for (int v = 0; v < 4; ++v) {
+        ql[v] = Q[1][v] + 0.5 * lfo_sweby(Q[1][v] - Q[0][v], Q[2][v] - Q[1][v], beta);
+        qr[v] = Q[2][v] - 0.5 * lfo_sweby(Q[2][v] - Q[1][v], Q[3][v] - Q[2][v], beta);
+    }
+    lfo_cons_to_prim(gamma, ql, wl);
+    lfo_cons_to_prim(gamma, qr, wr);
+    double us, ps;
+    lfo_acoustic_solve(gamma, wl[0], wl[1], wl[3], wr[0], wr[1], wr[3], &us, &ps);
+    const double *qa = (us > 0.0) ? ql : qr;
+    phi[0] = qa[0] * us;
+    phi[1] = qa[1] * us + ps;
+    phi[2] = qa[2] * us;
+    phi[3] = (qa[3] + ps) * us;
+}
+
+/* Flux of rho y_k under the conservative reconstruction: rho y_k itself is
+ * reconstructed, and crosses the face from the upwind side of u* (the same
+ * u* as stencil_face_cons). */
+static double species_face_flux_cons(double gamma, double beta, const double Q[4][4],
+                                     const double Y[4])
+{
+    double ql[4], qr[4], wl[4], wr[4];
+    for (int v = 0; v < 4; ++v) {
+        ql[v] = Q[1][v] + 0.5 * lfo_sweby(Q[1][v] - Q[0][v], Q[2][v] - Q[1][v], beta);
+        qr[v] = Q[2][v] - 0.5 * lfo_sweby(Q[2][v] - Q[1][v], Q[3][v] - Q[2][v], beta);
+    }
+    lfo_cons_to_prim(gamma, ql, wl);
+    lfo_cons_to_prim(gamma, qr, wr);
+    double us, ps;
+    lfo_acoustic_solve(gamma, wl[0], wl[1], wl[3], wr[0], wr[1], wr[3], &us, &ps);
+    double yl = Y[1] + 0.5 * lfo_sweby(Y[1] - Y[0], Y[2] - Y[1], beta);
+    double yr = Y[2] - 0.5 * lfo_sweby(Y[2] - Y[1], Y[3] - Y[2], beta);
+    return ((us > 0.0) ? yl : yr) * us;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid helpers                                                             */
 /* ------------------------------------------------------------------------ */
@@ -246,6 +290,7 @@ static int check_params(const lfo_params *P)
     if (!(P->beta >= 0.0 && P->beta <= 2.0)) return 0;
     if (!(P->cfl > 0.0)) return 0;
     if (P->ns < 0 || P->ns > LFO_MAX_SPECIES) return 0;
+    if (P->recon != LFO_RECON_PRIMITIVE && P->recon != LFO_RECON_CONSERVATIVE) return 0;
     if ((P->bc_x != LFO_BC_PERIODIC && P->bc_x != LFO_BC_TRANSMISSIVE) ||
         (P->bc_y != LFO_BC_PERIODIC && P->bc_y != LFO_BC_TRANSMISSIVE))
         return 0;
@@ -355,15 +400,25 @@ int lfo_residual(const lfo_params *P, const double *U, double *R)
             double W[4][4], phi[4];
             int64_t cell[4];
             gather_x(P, w, j, k, W, cell);
-            stencil_face(P->gamma, P->beta, W, phi, NULL);
+            double Q[4][4];
+            if (P->recon == LFO_RECON_CONSERVATIVE) {
+                for (int t = 0; t < 4; ++t)
+                    for (int c = 0; c < 4; ++c)
+                        Q[t][c] = U[XFIELD[c] * N + cell[t]];
+                stencil_face_cons(P->gamma, P->beta, Q, phi);
+            } else {
+                stencil_face(P->gamma, P->beta, W, phi, NULL);
+            }
             for (int c = 0; c < 4; ++c)
                 Fx[XFIELD[c] * NFx + (int64_t)j * (nx + 1) + k] = phi[c];
             for (int sp = 0; sp < P->ns; ++sp) {
                 double Y[4];
+                const int cons = P->recon == LFO_RECON_CONSERVATIVE;
                 for (int t = 0; t < 4; ++t)
-                    Y[t] = w[(4 + sp) * N + cell[t]];
+                    Y[t] = cons ? U[(4 + sp) * N + cell[t]] : w[(4 + sp) * N + cell[t]];
                 Fx[(4 + sp) * NFx + (int64_t)j * (nx + 1) + k] =
-                    species_face_flux(P->gamma, P->beta, W, Y);
+                    cons ? species_face_flux_cons(P->gamma, P->beta, Q, Y)
+                         : species_face_flux(P->gamma, P->beta, W, Y);
             }
         }
     }
@@ -373,15 +428,25 @@ int lfo_residual(const lfo_params *P, const double *U, double *R)
             double W[4][4], phi[4];
             int64_t cell[4];
             gather_y(P, w, i, k, W, cell);
-            stencil_face(P->gamma, P->beta, W, phi, NULL);
+            double Q[4][4];
+            if (P->recon == LFO_RECON_CONSERVATIVE) {
+                for (int t = 0; t < 4; ++t)
+                    for (int c = 0; c < 4; ++c)
+                        Q[t][c] = U[YFIELD[c] * N + cell[t]];
+                stencil_face_cons(P->gamma, P->beta, Q, phi);
+            } else {
+                stencil_face(P->gamma, P->beta, W, phi, NULL);
+            }
             for (int c = 0; c < 4; ++c)
                 Gy[YFIELD[c] * NGy + (int64_t)k * nx + i] = phi[c];
             for (int sp = 0; sp < P->ns; ++sp) {
                 double Y[4];
+                const int cons = P->recon == LFO_RECON_CONSERVATIVE;
                 for (int t = 0; t < 4; ++t)
-                    Y[t] = w[(4 + sp) * N + cell[t]];
+                    Y[t] = cons ? U[(4 + sp) * N + cell[t]] : w[(4 + sp) * N + cell[t]];
                 Gy[(4 + sp) * NGy + (int64_t)k * nx + i] =
-                    species_face_flux(P->gamma, P->beta, W, Y);
+                    cons ? species_face_flux_cons(P->gamma, P->beta, Q, Y)
+                         : species_face_flux(P->gamma, P->beta, W, Y);
             }
         }
     }
@@ -559,7 +624,7 @@ static void prim_tangent(const lfo_params *P, const double *U, const double *dU,
 int lfo_residual_jvp(const lfo_params *P, const double *U, const double *dU, double *out)
 {
     if (!check_params(P) || !U || !dU || !out) return LFO_ERR_ARG;
-    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
+    if (P->ns != 0 || P->recon != LFO_RECON_PRIMITIVE) return LFO_ERR_ARG; /* Euler fields, Sec. 5 reconstruction */
     const int nx = P->nx, ny = P->ny;
     const int64_t N = (int64_t)nx * ny;
     const int64_t NFx = (int64_t)ny * (nx + 1), NGy = (int64_t)(ny + 1) * nx;
@@ -625,7 +690,7 @@ int lfo_residual_jvp(const lfo_params *P, const double *U, const double *dU, dou
 int lfo_residual_vjp(const lfo_params *P, const double *U, const double *g, double *out)
 {
     if (!check_params(P) || !U || !g || !out) return LFO_ERR_ARG;
-    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
+    if (P->ns != 0 || P->recon != LFO_RECON_PRIMITIVE) return LFO_ERR_ARG; /* Euler fields, Sec. 5 reconstruction */
     const int nx = P->nx, ny = P->ny;
     const int64_t N = (int64_t)nx * ny;
     double *w = (double *)malloc(sizeof(double) * 4 * N);
@@ -705,7 +770,7 @@ int lfo_tlm_step(const lfo_params *P, const double *Un, double dt,
                  const double *dUn, double *dUnp1)
 {
     if (!check_params(P) || !Un || !dUn || !dUnp1) return LFO_ERR_ARG;
-    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
+    if (P->ns != 0 || P->recon != LFO_RECON_PRIMITIVE) return LFO_ERR_ARG; /* Euler fields, Sec. 5 reconstruction */
     const int64_t M = 4 * (int64_t)P->nx * P->ny;
     double *Rn = (double *)malloc(sizeof(double) * M);
     double *Us = (double *)malloc(sizeof(double) * M);
@@ -737,7 +802,7 @@ int lfo_adjoint_step(const lfo_params *P, const double *Un, double dt,
                      const double *lam_np1, double *lam_n)
 {
     if (!check_params(P) || !Un || !lam_np1 || !lam_n) return LFO_ERR_ARG;
-    if (P->ns != 0) return LFO_ERR_ARG; /* Euler fields only */
+    if (P->ns != 0 || P->recon != LFO_RECON_PRIMITIVE) return LFO_ERR_ARG; /* Euler fields, Sec. 5 reconstruction */
     const int64_t M = 4 * (int64_t)P->nx * P->ny;
     double *Rn = (double *)malloc(sizeof(double) * M);
     double *Us = (double *)malloc(sizeof(double) * M);

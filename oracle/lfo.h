@@ -23,6 +23,10 @@
  *  - MUSCL reconstruction of the primitive variables (rho, u, v, p),
  *    dimension by dimension; the upwind interface state is the
  *    conservative vector of the reconstructed upwind primitive state.
+ *    The conservative-variable reconstruction (recon = 1) is an ablation:
+ *    it limits (rho, rho u, rho v, rho E) instead, converts the face
+ *    states to primitive variables for the acoustic solve and upwinds the
+ *    reconstructed conservative vector.
  *  - The CFL time step is dt = cfl / max_K[(|u|+c)/dx + (|v|+c)/dy].
  *  - Boundary conditions per axis: periodic (index wrap) or transmissive
  *    (index clamp: ghost cells copy the edge cell).
@@ -58,7 +62,12 @@ typedef struct {
     int32_t ns;          /* passive mass fractions, 0..LFO_MAX_SPECIES: the
                             state then holds 4 + ns fields, field 4 + k
                             being rho y_k                                    */
+    int32_t recon;       /* LFO_RECON_PRIMITIVE (Sec. 5: rho, u, v, p and
+                            y_k) or LFO_RECON_CONSERVATIVE (rho, rho u,
+                            rho v, rho E and rho y_k; the ablation)           */
 } lfo_params;
+
+enum { LFO_RECON_PRIMITIVE = 0, LFO_RECON_CONSERVATIVE = 1 };
 
 #define LFO_MAX_SPECIES 8
 
@@ -113,7 +122,8 @@ void lfo_totals(const lfo_params *P, const double *U, double *out);
 
 /* Jacobian-vector product J_R(U) dU, and vector-Jacobian product
  * J_R(U)^T g, of the residual R.  These and the tangent-linear and adjoint
- * steps below cover the Euler fields only: LFO_ERR_ARG when ns > 0. */
+ * steps below cover the Euler fields with primitive reconstruction only:
+ * LFO_ERR_ARG when ns > 0 or recon != LFO_RECON_PRIMITIVE. */
 int lfo_residual_jvp(const lfo_params *P, const double *U, const double *dU,
                      double *out);
 int lfo_residual_vjp(const lfo_params *P, const double *U, const double *g,

@@ -25,7 +25,7 @@ def params_from(cfg, **over):
     import oracle
     kw = dict(nx=cfg["nx"], ny=cfg["ny"], dx=cfg["dx"], dy=cfg["dy"], gamma=cfg["gamma"],
               cfl=cfg["cfl"], beta=cfg["beta"], bc_x=cfg["bc_x"], bc_y=cfg["bc_y"],
-              ns=cfg.get("ns", 0))
+              ns=cfg.get("ns", 0), recon=cfg.get("recon", 0))
     kw.update(over)
     return oracle.Params(**kw)
 

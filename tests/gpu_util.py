@@ -26,7 +26,7 @@ def solver_for(cfg, dtype="f64", **over):
 def oracle_params(cfg, **over):
     kw = dict(nx=cfg["nx"], ny=cfg["ny"], dx=cfg["dx"], dy=cfg["dy"], gamma=cfg["gamma"],
               cfl=cfg["cfl"], beta=cfg["beta"], bc_x=cfg["bc_x"], bc_y=cfg["bc_y"],
-              ns=cfg.get("ns", 0))
+              ns=cfg.get("ns", 0), recon=cfg.get("recon", 0))
     kw.update(over)
     return oracle.Params(**kw)
 
