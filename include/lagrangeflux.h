@@ -24,7 +24,8 @@
  *    rho*E), then f = 4..3+n_species for rho*y_k; j = 0..ny-1 the y index,
  *    i = 0..nx-1 the x index (fastest).  Element type is double (LF_F64) or
  *    float (LF_F32), per the context.  The adjoint entry points take the 4
- *    Euler fields only and require n_species == 0.
+ *    Euler fields only and require n_species == 0 and the primitive
+ *    reconstruction.
  *  - ws is a DEVICE workspace of at least the size lf_init reports, owned
  *    by the caller, 256-byte aligned.  It holds the predictor state U*, the
  *    adjoint intermediate, the reduction cells and the device-side dt / t /
@@ -62,6 +63,8 @@ typedef enum {
 typedef enum { LF_F64 = 0, LF_F32 = 1 } lf_dtype;
 
 #define LF_MAX_SPECIES 4
+
+typedef enum { LF_RECON_PRIMITIVE = 0, LF_RECON_CONSERVATIVE = 1 } lf_recon;
 typedef enum { LF_BC_PERIODIC = 0, LF_BC_TRANSMISSIVE = 1 } lf_bc;
 
 typedef struct {
@@ -78,6 +81,13 @@ typedef struct {
     int32_t dtype;    /* lf_dtype of every state / adjoint array                */
     int32_t n_species; /* passive mass fractions carried after the Euler
                          fields, 0 <= n_species <= LF_MAX_SPECIES            */
+    int32_t reconstruction; /* lf_recon: LF_RECON_PRIMITIVE, the paper's
+                         limited reconstruction of (rho, u, v, p) (Sec. 5),
+                         or LF_RECON_CONSERVATIVE, an ablation that limits
+                         (rho, rho u, rho v, rho E), converts the face states
+                         to primitive variables for eqs. (13)-(14) and
+                         upwinds the reconstructed conservative vector; the
+                         latter requires n_species == 0                     */
 } lf_params;
 
 /* Validates *params, creates a context and reports the workspace size in
@@ -142,7 +152,8 @@ int lf_advance(lf_ctx *ctx, void *U, double t0, double t_end, int64_t max_steps,
 int lf_residual(lf_ctx *ctx, const void *U, void *R, void *ws, void *stream);
 
 /* Vector-Jacobian product out = J_R(U)^T g of the residual, async
- * (contexts without mass fractions; LF_ERR_ARG otherwise).  The
+ * (contexts without mass fractions and with the primitive reconstruction;
+ * LF_ERR_ARG otherwise).  The
  * derivative conventions at the non-differentiable points are: limiter
  * derivative zero when ab <= 0, min follows its first argument on ties,
  * max(m1, m2) follows m1 on ties, max(c_L, c_R) follows c_L on ties, the
@@ -151,7 +162,8 @@ int lf_residual_vjp(lf_ctx *ctx, const void *U, const void *g, void *out, void *
                     void *stream);
 
 /* Adjoint of one lf_step at the frozen dt, async (contexts without mass
- * fractions; LF_ERR_ARG otherwise): given lam_np1 =
+ * fractions and with the primitive reconstruction; LF_ERR_ARG otherwise):
+ * given lam_np1 =
  * dJ/dU^{n+1}, writes lam_n = dJ/dU^n, recomputing U* from Un:
  *   mu    = (lam_np1 - dt J_R(U*)^T lam_np1) / 2
  *   lam_n = lam_np1 / 2 + mu - dt J_R(U^n)^T mu.

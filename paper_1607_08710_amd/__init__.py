@@ -26,6 +26,7 @@ LF_OK, LF_ERR_ARG, LF_ERR_HIP, LF_ERR_NONPHYSICAL, LF_ERR_STATE = 0, 1, 2, 3, 4
 LF_F64, LF_F32 = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
 LF_MAX_SPECIES = 4
+LF_RECON_PRIMITIVE, LF_RECON_CONSERVATIVE = 0, 1
 
 # Names exported by the C ABI (include/lagrangeflux.h).
 ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_stage", "lf_advance",
@@ -48,7 +49,7 @@ class lf_params(ctypes.Structure):
         ("dx", ctypes.c_double), ("dy", ctypes.c_double),
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("beta", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("dtype", ctypes.c_int32),
-        ("n_species", ctypes.c_int32),
+        ("n_species", ctypes.c_int32), ("reconstruction", ctypes.c_int32),
     ]
 
 
@@ -109,10 +110,11 @@ class Params:
     bc_y: int = PERIODIC
     dtype: int = LF_F64
     n_species: int = 0
+    reconstruction: int = LF_RECON_PRIMITIVE
 
     def c(self) -> lf_params:
         return lf_params(self.nx, self.ny, self.dx, self.dy, self.gamma, self.cfl, self.beta,
-                         self.bc_x, self.bc_y, self.dtype, self.n_species)
+                         self.bc_x, self.bc_y, self.dtype, self.n_species, self.reconstruction)
 
 
 def init(params: Params):

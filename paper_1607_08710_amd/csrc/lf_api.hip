@@ -35,6 +35,8 @@ bool params_ok(const lf_params* p) {
   if (p->bc_y != LF_BC_PERIODIC && p->bc_y != LF_BC_TRANSMISSIVE) return false;
   if (p->dtype != LF_F64 && p->dtype != LF_F32) return false;
   if (p->n_species < 0 || p->n_species > LF_MAX_SPECIES) return false;
+  if (p->reconstruction != LF_RECON_PRIMITIVE && p->reconstruction != LF_RECON_CONSERVATIVE) return false;
+  if (p->reconstruction == LF_RECON_CONSERVATIVE && p->n_species != 0) return false;
   return true;
 }
 
@@ -69,7 +71,8 @@ int lf_init(const lf_params* params, lf_ctx** out, size_t* workspace_bytes) {
   lf_ctx* c = new (std::nothrow) lf_ctx;
   if (!c) return LF_ERR_ARG;
   c->g = lf::make_grid(params->nx, params->ny, params->dx, params->dy, params->gamma, params->cfl,
-                       params->beta, params->bc_x, params->bc_y, params->dtype, params->n_species);
+                       params->beta, params->bc_x, params->bc_y, params->dtype, params->n_species,
+                       params->reconstruction);
   c->L = lf::make_layout(c->g);
   c->state_bytes = (size_t)(4 + params->n_species) * (size_t)params->nx * (size_t)params->ny *
                    (params->dtype == LF_F64 ? sizeof(double) : sizeof(float));
@@ -229,7 +232,7 @@ int lf_residual(lf_ctx* ctx, const void* U, void* R, void* ws, void* stream) {
 }
 
 int lf_residual_vjp(lf_ctx* ctx, const void* U, const void* g, void* out, void* ws, void* stream) {
-  if (!ctx || !U || !g || !out || !ws || ctx->g.ns != 0) return LF_ERR_ARG;
+  if (!ctx || !U || !g || !out || !ws || ctx->g.ns != 0 || ctx->g.recon != 0) return LF_ERR_ARG;
   const size_t n = ctx->state_bytes;
   if (overlap(out, n, U, n) || overlap(out, n, g, n) || overlap(out, n, ws, ctx->L.total))
     return LF_ERR_ARG;
@@ -239,7 +242,7 @@ int lf_residual_vjp(lf_ctx* ctx, const void* U, const void* g, void* out, void* 
 
 int lf_adjoint_step(lf_ctx* ctx, const void* Un, double dt, const void* lam_np1, void* lam_n, void* ws,
                     void* stream) {
-  if (!ctx || !Un || !lam_np1 || !lam_n || !ws || ctx->g.ns != 0) return LF_ERR_ARG;
+  if (!ctx || !Un || !lam_np1 || !lam_n || !ws || ctx->g.ns != 0 || ctx->g.recon != 0) return LF_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return LF_ERR_ARG;
   const size_t n = ctx->state_bytes, w = ctx->L.total;
   if (overlap(lam_n, n, Un, n) || overlap(lam_n, n, lam_np1, n)) return LF_ERR_ARG;

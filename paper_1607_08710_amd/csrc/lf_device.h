@@ -134,6 +134,16 @@ __device__ __forceinline__ Prim<T> to_prim(T q0, T q1, T q2, T q3, T gm1) {
   return w;
 }
 
+// Variables a cell is reconstructed in: the primitive (rho, u, v, p) of
+// Sec. 5, or, for the conservative-variable ablation (CONS), the
+// conservative (rho, rho u, rho v, rho E) themselves (kept in the same
+// fields r, u, v, p).
+template <bool CONS, typename T>
+__device__ __forceinline__ Prim<T> rec_vars(T q0, T q1, T q2, T q3, T gm1) {
+  if constexpr (CONS) return {q0, q1, q2, q3};
+  else return to_prim(q0, q1, q2, q3, gm1);
+}
+
 // ---- Sweby limiter, eq. (sweby) ---------------------------------------------
 
 // For beta >= 1 the max-min of eq. (sweby) equals min(beta min(|a|,|b|),
@@ -180,6 +190,22 @@ template <typename T>
 struct FaceState {
   T r, un, ut, p;
 };
+
+// A reconstructed face state as primitive variables: unchanged for the
+// primitive reconstruction; for the conservative one (rho, rho u_n,
+// rho u_t, rho E) -> (rho, u_n, u_t, p) by the perfect-gas law (the same
+// arithmetic as to_prim).
+template <bool CONS, typename T>
+__device__ __forceinline__ FaceState<T> face_prim(const FaceState<T>& f, T gm1) {
+  if constexpr (!CONS) {
+    return f;
+  } else {
+    const T ir = rcp(f.r);
+    const T un = f.un * ir, ut = f.ut * ir;
+    const T ke = T(0.5) * (f.un * un + f.ut * ut);
+    return {f.r, un, ut, gm1 * (f.p - ke)};
+  }
+}
 
 template <typename T>
 struct Flux {

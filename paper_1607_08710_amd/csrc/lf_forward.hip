@@ -41,8 +41,9 @@ struct Frac {
   T v[NS > 0 ? NS : 1];
 };
 
-template <typename T, int MODE, int BCX, int BCY, int NS>
+template <typename T, int MODE, int BCX, int BCY, int NS, bool CONS>
 __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(StageArgs<T> a) {
+  static_assert(!CONS || NS == 0, "the conservative reconstruction is built without mass fractions");
   constexpr int WPB = waves_per_block<T>();
   constexpr int NF = 4 + NS;  // conservative fields: Euler, then rho*y_k
   if (a.dt_dev && a.ctl->done) return;
@@ -156,10 +157,10 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       load_base(o0, BA);
       if (y0 + 1 < y1) load_base(o0 + nx, BB);
     }
-    Prim<T> wa = to_prim(qa[0], qa[1], qa[2], qa[3], gm1);
-    Prim<T> wb = to_prim(qb[0], qb[1], qb[2], qb[3], gm1);
-    W0 = to_prim(q0[0], q0[1], q0[2], q0[3], gm1);
-    W1 = to_prim(q1[0], q1[1], q1[2], q1[3], gm1);
+    Prim<T> wa = rec_vars<CONS>(qa[0], qa[1], qa[2], qa[3], gm1);
+    Prim<T> wb = rec_vars<CONS>(qb[0], qb[1], qb[2], qb[3], gm1);
+    W0 = rec_vars<CONS>(q0[0], q0[1], q0[2], q0[3], gm1);
+    W1 = rec_vars<CONS>(q1[0], q1[1], q1[2], q1[3], gm1);
     ring_put(y0, q0);
     ring_put(y0 + 1, q1);
     Prim<T> d_lo = sub(wb, wa);    // y0 - 3/2
@@ -167,7 +168,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     Prim<T> s_b = slope(d_lo, d_mid, beta);
     Sg0 = slope(d_mid, sub(W1, W0), beta);
     bool gl;
-    Gf0 = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(W0, Sg0), gam, igm1, gl);
+    Gf0 = face_flux(face_prim<CONS>(face_plus<T, true>(wb, s_b), gm1),
+                    face_prim<CONS>(face_minus<T, true>(W0, Sg0), gm1), gam, igm1, gl);
     if constexpr (NS > 0) {
       const Frac<T, NS> ya = fractions(qa), yb = fractions(qb);
       Y0 = fractions(q0);
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
                  Prim<T>& so1, const Flux<T>& Gp, Flux<T>& G, Frac<T, NS>& yo, const Frac<T, NS>& yo1,
                  const Frac<T, NS>& syo, Frac<T, NS>& syo1, const Frac<T, NS>& gyp, Frac<T, NS>& gy) {
     const int off = o * nx + cm;
-    const Prim<T> wn = to_prim(qc[0], qc[1], qc[2], qc[3], gm1);
+    const Prim<T> wn = rec_vars<CONS>(qc[0], qc[1], qc[2], qc[3], gm1);
     const Frac<T, NS> yn = fractions(qc);
     ring_put(o + 2, qc);
     if (o + 3 <= y1) load_row(o + 4, qc);
@@ -202,7 +204,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const Prim<T> dlo = sub(wo1, wo);
     so1 = slope(dlo, sub(wn, wo1), beta);
     bool gl;
-    G = face_flux(face_plus<T, true>(wo, so), face_minus<T, true>(wo1, so1), gam, igm1, gl);
+    G = face_flux(face_prim<CONS>(face_plus<T, true>(wo, so), gm1),
+                  face_prim<CONS>(face_minus<T, true>(wo1, so1), gm1), gam, igm1, gl);
 
     // x: slopes of row o from lane neighbours, flux through face c+1/2
     const Prim<T> wr1 = shl1(wo);       // w_{c+1}
@@ -211,7 +214,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const Prim<T> sx = slope(dxm, dxp, beta);
     const Prim<T> sx1 = shl1(sx);       // sigma_{c+1}
     bool fl;
-    const Flux<T> F = face_flux(face_plus<T, false>(wo, sx), face_minus<T, false>(wr1, sx1), gam, igm1, fl);
+    const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(wo, sx), gm1),
+                                face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1, fl);
     const Flux<T> Fm = shr1(F);         // flux through face c-1/2
 
     // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11),
@@ -462,7 +466,7 @@ __global__ __launch_bounds__(256) void totals_final_kernel(const double* __restr
 
 // ---- host launchers -----------------------------------------------------------
 
-template <typename T, int MODE, int BCX, int BCY, int NS>
+template <typename T, int MODE, int BCX, int BCY, int NS, bool CONS>
 static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base, void* out, double dt,
                                  Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
   StageArgs<T> a;
@@ -489,7 +493,7 @@ static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;
-  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY, NS>), dim3(g.blocks_pad),
+  hipLaunchKernelGGL((stage_kernel<T, MODE, BCX, BCY, NS, CONS>), dim3(g.blocks_pad),
                      dim3(kWave * waves_per_block<T>()), 0, s, a);
   return hipGetLastError();
 }
@@ -498,12 +502,13 @@ template <typename T, int MODE, int BCX, int BCY>
 static hipError_t launch_stage_ns(const Grid& g, const void* in, const void* base, void* out, double dt,
                                   Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s) {
   static_assert(kMaxSpecies == 4, "one instantiation per species count");
+  if (g.recon) return launch_stage_t<T, MODE, BCX, BCY, 0, true>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
   switch (g.ns) {
-    case 0: return launch_stage_t<T, MODE, BCX, BCY, 0>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
-    case 1: return launch_stage_t<T, MODE, BCX, BCY, 1>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
-    case 2: return launch_stage_t<T, MODE, BCX, BCY, 2>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
-    case 3: return launch_stage_t<T, MODE, BCX, BCY, 3>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
-    default: return launch_stage_t<T, MODE, BCX, BCY, 4>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 0: return launch_stage_t<T, MODE, BCX, BCY, 0, false>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 1: return launch_stage_t<T, MODE, BCX, BCY, 1, false>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 2: return launch_stage_t<T, MODE, BCX, BCY, 2, false>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    case 3: return launch_stage_t<T, MODE, BCX, BCY, 3, false>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
+    default: return launch_stage_t<T, MODE, BCX, BCY, 4, false>(g, in, base, out, dt, ctl, dt_dev, reduce, s);
   }
 }
 
@@ -591,9 +596,10 @@ hipError_t launch_totals(const Grid& g, const Layout& L, const void* U, void* ws
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, double beta, int bc_x,
-               int bc_y, int dtype, int ns) {
+               int bc_y, int dtype, int ns, int recon) {
   Grid g;
   g.ns = ns;
+  g.recon = recon;
   g.nx = nx;
   g.ny = ny;
   g.dx = dx;

@@ -52,14 +52,15 @@ struct Win {
 };
 
 // Window of row a from the primitive rows a-2 .. a+1.
-template <typename T>
+template <bool CONS, typename T>
 __device__ __forceinline__ Win<T> prime_window(const Prim<T>& wa, const Prim<T>& wb, const Prim<T>& w0,
-                                               const Prim<T>& w1, T beta, T gam, T igm1) {
+                                               const Prim<T>& w1, T beta, T gam, T gm1, T igm1) {
   Win<T> W;
   const Prim<T> d_mid = sub(w0, wb);
   const Prim<T> s_b = slope(sub(wb, wa), d_mid, beta);
   W.s0 = slope(d_mid, sub(w1, w0), beta);
-  W.g = face_flux(face_plus<T, true>(wb, s_b), face_minus<T, true>(w0, W.s0), gam, igm1);
+  W.g = face_flux(face_prim<CONS>(face_plus<T, true>(wb, s_b), gm1),
+                  face_prim<CONS>(face_minus<T, true>(w0, W.s0), gm1), gam, igm1);
   W.w0 = w0;
   W.w1 = w1;
   return W;
@@ -68,17 +69,19 @@ __device__ __forceinline__ Win<T> prime_window(const Prim<T>& wa, const Prim<T>&
 // Residual of eq. (11) for row a of the window (every lane; valid two lanes
 // inside the valid input), given primitive row a+2; slides the window by a
 // row.  Same arithmetic, in the same order, as the stage kernel's row.
-template <typename T>
-__device__ __forceinline__ void window_row(Win<T>& W, const Prim<T>& wn, T beta, T gam, T igm1, T kxy,
+template <bool CONS, typename T>
+__device__ __forceinline__ void window_row(Win<T>& W, const Prim<T>& wn, T beta, T gam, T gm1, T igm1, T kxy,
                                            T idx, T (&r)[4]) {
   const Prim<T> s1 = slope(sub(W.w1, W.w0), sub(wn, W.w1), beta);
-  const Flux<T> G = face_flux(face_plus<T, true>(W.w0, W.s0), face_minus<T, true>(W.w1, s1), gam, igm1);
+  const Flux<T> G = face_flux(face_prim<CONS>(face_plus<T, true>(W.w0, W.s0), gm1),
+                              face_prim<CONS>(face_minus<T, true>(W.w1, s1), gm1), gam, igm1);
   const Prim<T> wr1 = shl1(W.w0);
   const Prim<T> dxp = sub(wr1, W.w0);
   const Prim<T> dxm = shr1(dxp);
   const Prim<T> sx = slope(dxm, dxp, beta);
   const Prim<T> sx1 = shl1(sx);
-  const Flux<T> F = face_flux(face_plus<T, false>(W.w0, sx), face_minus<T, false>(wr1, sx1), gam, igm1);
+  const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(W.w0, sx), gm1),
+                              face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1);
   const Flux<T> Fm = shr1(F);
   r[0] = fma(G.f0 - W.g.f0, kxy, F.f0 - Fm.f0) * idx;
   r[1] = fma(G.f2 - W.g.f2, kxy, F.f1 - Fm.f1) * idx;
@@ -96,7 +99,7 @@ __device__ __forceinline__ void window_row(Win<T>& W, const Prim<T>& wn, T beta,
 // rows waiting for the corrector's combination stays in registers, and one
 // LDS row of U* serves the reads across lanes.  Results are stored straight
 // from the lanes (no staging, no block barrier).
-template <typename T, int BCX, int BCY>
+template <typename T, int BCX, int BCY, bool CONS>
 __global__ __launch_bounds__(kWave * waves_per_block<T>())
 void fused_step_kernel(FusedArgs<T> a) {
   constexpr int WPB = waves_per_block<T>();
@@ -170,9 +173,10 @@ void fused_step_kernel(FusedArgs<T> a) {
     if (plo + 3 <= nlast) load_row(plo + 3, QB);
     put_n(plo, q0);
     put_n(plo + 1, q1);
-    PW = prime_window(to_prim(qa[0], qa[1], qa[2], qa[3], gm1), to_prim(qb[0], qb[1], qb[2], qb[3], gm1),
-                      to_prim(q0[0], q0[1], q0[2], q0[3], gm1), to_prim(q1[0], q1[1], q1[2], q1[3], gm1),
-                      beta, gam, igm1);
+    PW = prime_window<CONS>(rec_vars<CONS>(qa[0], qa[1], qa[2], qa[3], gm1),
+                            rec_vars<CONS>(qb[0], qb[1], qb[2], qb[3], gm1),
+                            rec_vars<CONS>(q0[0], q0[1], q0[2], q0[3], gm1),
+                            rec_vars<CONS>(q1[0], q1[1], q1[2], q1[3], gm1), beta, gam, gm1, igm1);
   }
   int pr = plo;  // next U* row to produce
   // U* of the last two rows produced (conservative, this lane's column):
@@ -181,13 +185,13 @@ void fused_step_kernel(FusedArgs<T> a) {
   // U* row pr = U^n - dt R(U^n); it goes to S1 (S1 moves to S0) and to the
   // LDS row read across lanes
   auto produce = [&]() {
-    const Prim<T> wn = to_prim(QA[0], QA[1], QA[2], QA[3], gm1);  // U^n row pr+2
+    const Prim<T> wn = rec_vars<CONS>(QA[0], QA[1], QA[2], QA[3], gm1);  // U^n row pr+2
     put_n(pr + 2, QA);
 #pragma unroll
     for (int f = 0; f < 4; ++f) QA[f] = QB[f];
     if (pr + 4 <= nlast) load_row(pr + 4, QB);
     T res[4];
-    window_row(PW, wn, beta, gam, igm1, kxy, idx, res);
+    window_row<CONS>(PW, wn, beta, gam, gm1, igm1, kxy, idx, res);
     const int sn = nslot(pr);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -201,7 +205,7 @@ void fused_step_kernel(FusedArgs<T> a) {
   // lanes: the edge column)
   auto star_prim = [&]() {
     __builtin_amdgcn_wave_barrier();
-    return to_prim(my_s[0][src], my_s[1][src], my_s[2][src], my_s[3][src], gm1);
+    return rec_vars<CONS>(my_s[0][src], my_s[1][src], my_s[2][src], my_s[3][src], gm1);
   };
 
   // ---- corrector: window of row y0 from U* rows y0-2 .. y0+1 ----
@@ -214,7 +218,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     while (pr <= r) produce();
     cw[k] = star_prim();
   }
-  Win<T> CW = prime_window(cw[0], cw[1], cw[2], cw[3], beta, gam, igm1);
+  Win<T> CW = prime_window<CONS>(cw[0], cw[1], cw[2], cw[3], beta, gam, gm1, igm1);
   // U* (conservative) of the rows the corrector combines next: row o in C0,
   // row o+1 in C1
   T C0[4], C1[4];
@@ -238,7 +242,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     if (fresh) produce();
     const Prim<T> wn = star_prim();  // U* row rmap(o+2), the newest produced
     T res[4];
-    window_row(CW, wn, beta, gam, igm1, kxy, idx, res);
+    window_row<CONS>(CW, wn, beta, gam, gm1, igm1, kxy, idx, res);
     const int sn = nslot(o);
     T u[4];
 #pragma unroll
@@ -298,7 +302,7 @@ static int fused_rows(int nx, int ny) {
   return r > ny ? ny : r;
 }
 
-template <typename T, int BCX, int BCY>
+template <typename T, int BCX, int BCY, bool CONS>
 static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                                  bool reduce, hipStream_t s) {
   constexpr int WPB = waves_per_block<T>();
@@ -325,28 +329,31 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, doubl
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;
-  hipLaunchKernelGGL((fused_step_kernel<T, BCX, BCY>), dim3(a.blocks_pad), dim3(kWave * WPB), 0, s, a);
+  hipLaunchKernelGGL((fused_step_kernel<T, BCX, BCY, CONS>), dim3(a.blocks_pad), dim3(kWave * WPB), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool CONS>
 static hipError_t launch_fused_bc(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                                   bool reduce, hipStream_t s) {
   if (g.bc_x == kBcPeriodic) {
     if (g.bc_y == kBcPeriodic)
-      return launch_fused_t<T, kBcPeriodic, kBcPeriodic>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    return launch_fused_t<T, kBcPeriodic, kBcTransmissive>(g, in, out, dt, ctl, dt_dev, reduce, s);
+      return launch_fused_t<T, kBcPeriodic, kBcPeriodic, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    return launch_fused_t<T, kBcPeriodic, kBcTransmissive, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
   }
   if (g.bc_y == kBcPeriodic)
-    return launch_fused_t<T, kBcTransmissive, kBcPeriodic>(g, in, out, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_t<T, kBcTransmissive, kBcTransmissive>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    return launch_fused_t<T, kBcTransmissive, kBcPeriodic, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  return launch_fused_t<T, kBcTransmissive, kBcTransmissive, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
 }
 
 hipError_t launch_fused_step(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                              bool reduce, hipStream_t s) {
   if (g.ns != 0) return hipErrorInvalidValue;  // states with mass fractions take the two-stage path
-  if (g.dtype == 0) return launch_fused_bc<double>(g, in, out, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_bc<float>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  if (g.dtype == 0)
+    return g.recon ? launch_fused_bc<double, true>(g, in, out, dt, ctl, dt_dev, reduce, s)
+                   : launch_fused_bc<double, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  return g.recon ? launch_fused_bc<float, true>(g, in, out, dt, ctl, dt_dev, reduce, s)
+                 : launch_fused_bc<float, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
 }
 
 }  // namespace lf

@@ -17,6 +17,7 @@ struct Grid {
   int bc_x, bc_y;
   int dtype;            // 0 = double, 1 = float
   int ns;               // passive mass fractions carried after the 4 Euler fields
+  int recon;            // 0: primitive reconstruction (Sec. 5), 1: conservative
   int tiles_x, tiles_y; // wave tiles of kTileW columns x rows_per_wave rows
   int rows_per_wave;
   int wpb;              // waves per stage block (a block is wpb adjacent tiles)
@@ -35,7 +36,7 @@ struct Layout {
 };
 
 Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, double beta,
-               int bc_x, int bc_y, int dtype, int ns);
+               int bc_x, int bc_y, int dtype, int ns, int recon);
 Layout make_layout(const Grid& g);
 
 

@@ -18,7 +18,8 @@ def solver_for(cfg, dtype="f64", **over):
     import paper_1607_08710_amd as L
     kw = dict(nx=cfg["nx"], ny=cfg["ny"], dx=cfg["dx"], dy=cfg["dy"], gamma=cfg["gamma"],
               cfl=cfg["cfl"], beta=cfg["beta"], bc_x=cfg["bc_x"], bc_y=cfg["bc_y"],
-              dtype=L.LF_F64 if dtype == "f64" else L.LF_F32, n_species=cfg.get("ns", 0))
+              dtype=L.LF_F64 if dtype == "f64" else L.LF_F32, n_species=cfg.get("ns", 0),
+              reconstruction=cfg.get("recon", 0))
     kw.update(over)
     return L.Solver(L.Params(**kw))
 

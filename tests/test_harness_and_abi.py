@@ -63,7 +63,8 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(dx=0.0), dict(dy=float("nan")),
                                  dict(gamma=1.0), dict(gamma=3.5), dict(beta=-0.1), dict(beta=2.5), dict(beta=0.5),
                                  dict(cfl=0.0), dict(bc_x=2), dict(bc_y=-1), dict(dtype=7),
-                                 dict(nx=65536, ny=65536), dict(n_species=-1), dict(n_species=5)])
+                                 dict(nx=65536, ny=65536), dict(n_species=-1), dict(n_species=5),
+                                 dict(reconstruction=2), dict(reconstruction=1, n_species=1)])
 def test_init_rejects(bad):
     import paper_1607_08710_amd as L
     with pytest.raises(L.LFError) as e:
@@ -134,6 +135,19 @@ def test_species_context_validation():
     assert lib.lf_residual(ctx, A, vp(0x1000000 + state - 8), W, None) == E
     assert lib.lf_residual_vjp(ctx, A, B, C, W, None) == E
     assert lib.lf_adjoint_step(ctx, A, 0.1, B, C, W, None) == E
+    lib.lf_destroy(ctx)
+
+
+def test_conservative_reconstruction_context_validation():
+    """The conservative-reconstruction ablation has no adjoint: both
+    adjoint entry points refuse the context before any HIP call."""
+    import paper_1607_08710_amd as L
+    lib = L.lib()
+    ctx, ws = L.init(_params(reconstruction=L.LF_RECON_CONSERVATIVE))
+    vp = ctypes.c_void_p
+    A, B, C, W = vp(0x1000000), vp(0x2000000), vp(0x3000000), vp(0x10000000)
+    assert lib.lf_residual_vjp(ctx, A, B, C, W, None) == L.LF_ERR_ARG
+    assert lib.lf_adjoint_step(ctx, A, 0.1, B, C, W, None) == L.LF_ERR_ARG
     lib.lf_destroy(ctx)
 
 
