@@ -69,7 +69,8 @@ def kernel_source_hash() -> str:
 
 def make_solver(L, cfg, dtype):
     return L.Solver(L.Params(cfg["nx"], cfg["ny"], cfg["dx"], cfg["dy"], cfg["gamma"], cfg["cfl"],
-                             cfg["beta"], cfg["bc_x"], cfg["bc_y"], dtype, cfg.get("ns", 0)))
+                             cfg["beta"], cfg["bc_x"], cfg["bc_y"], dtype, cfg.get("ns", 0),
+                             cfg.get("recon", 0)))
 
 
 def time_advance(S, U, steps, warmup):
@@ -130,11 +131,12 @@ def time_single_pass(S, U, reps):
     return ms / 1e3
 
 
-def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0):
+def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0, recon=0):
     import torch
     tdt = torch.float64 if dtype_flag == L.LF_F64 else torch.float32
     esz = 8 if dtype_flag == L.LF_F64 else 4
     U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=fractions)
+    cfg["recon"] = recon
     S = make_solver(L, cfg, dtype_flag)
     tot0 = S.totals(U)
     sec, wall = time_advance(S, U, steps, warmup)
@@ -152,6 +154,8 @@ def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0):
         "corrector_GBps": fw * BYTES_PER_CELL[("corrector", esz)] * cells / corr / 1e9,
         "totals_initial": [float(a) for a in tot0], "totals_drift": drift,
     }
+    if recon:
+        res["reconstruction"] = "conservative (rho, rho u, rho v, rho E)"
     if fractions:
         # lf_advance runs the two stages when the state carries fractions
         res["fractions"] = fractions
@@ -327,7 +331,7 @@ def main():
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
     f64 = f32 = adj64 = adj32 = roofline = cpu = None
-    species = roofline_two_stage = None
+    species = roofline_two_stage = recon64 = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
         f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
@@ -369,6 +373,10 @@ def main():
                             fractions=k)
             species[f"f64_ns{k}"] = r
             log(f"  {r['value'] / 1e9:.2f} G cell-updates/s, corrector {r['corrector_GBps']:.0f} GB/s")
+    if "species" in legs:
+        log(f"FP64 Kelvin-Helmholtz {args.n}^2, conservative-variable reconstruction: {args.species_steps} steps")
+        recon64 = forward_leg(L, W, args.n, L.LF_F64, args.species_steps, args.warmup, args.kernel_reps, recon=1)
+        log(f"  {recon64['value'] / 1e9:.2f} G cell-updates/s")
     if "adjoint" in legs:
         log(f"adjoint {args.adj_n}^2, {args.adj_steps} steps, checkpoints every {args.adj_ckpt}")
         adj64 = adjoint_leg(L, W, args.adj_n, L.LF_F64, args.adj_steps, args.adj_ckpt, 10)
@@ -403,6 +411,7 @@ def main():
         "fp64": f64,
         "fp32": f32,
         "species": species,
+        "conservative_reconstruction": recon64,
         "adjoint": {"n": args.adj_n, "steps": args.adj_steps, "ckpt_every": args.adj_ckpt,
                     "f64": adj64, "f32": adj32},
         "paper_context": {"value": 81.0e6, "unit": "cell-updates/s",
