@@ -121,9 +121,9 @@ int lf_step(lf_ctx* ctx, const void* Un, void* Unp1, double dt, void* ws, void* 
   if (Un != Unp1 && overlap(Un, n, Unp1, n)) return LF_ERR_ARG;
   if (overlap(Un, n, ws, ctx->L.total) || overlap(Unp1, n, ws, ctx->L.total)) return LF_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // single pass when the output is a separate buffer; in place (and with
-  // mass fractions) the two stages, through U* in the workspace
-  if (Un != Unp1 && ctx->g.ns == 0)
+  // single pass when the output is a separate buffer; in place the two
+  // stages, through U* in the workspace
+  if (Un != Unp1)
     return hip_status(lf::launch_fused_step(ctx->g, Un, Unp1, dt, nullptr, false, false, s));
   void* us = ustar_of(ctx, ws);
   hipError_t e = lf::launch_stage(ctx->g, lf::kPredictor, Un, nullptr, us, dt, nullptr, false, false, s);
@@ -165,12 +165,12 @@ int lf_advance(lf_ctx* ctx, void* U, double t0, double t_end, int64_t max_steps,
   int rc = read_ctl(ctl, &h, s);
   if (rc != LF_OK) return rc;
 
-  // Without mass fractions each step is one single-pass launch that
-  // alternates between U and the U* buffer of the workspace (launch j reads
-  // buffer j % 2); launches after the device marks the loop done return at
-  // once, so the result is in buffer (steps % 2) and is copied back to U at
-  // the end when that is the workspace.
-  const bool fused = ctx->g.ns == 0;
+  // Each step is one single-pass launch that alternates between U and the
+  // U* buffer of the workspace (launch j reads buffer j % 2); launches after
+  // the device marks the loop done return at once, so the result is in
+  // buffer (steps % 2) and is copied back to U at the end when that is the
+  // workspace.
+  const bool fused = true;
   void* buf[2] = {U, us};
   long long launched = 0;
   long long done_steps = 0;

@@ -325,6 +325,12 @@ __device__ __forceinline__ void face_flux_vjp(const FaceState<T>& L, const FaceS
 
 // ---- pieces of a stage row shared by the stage kernels ----------------------
 
+// Mass fractions of one row (NS of them; one unused slot when NS = 0).
+template <typename T, int NS>
+struct Frac {
+  T v[NS > 0 ? NS : 1];
+};
+
 template <typename T>
 __device__ __forceinline__ Prim<T> sub(const Prim<T>& a, const Prim<T>& b) {
   return {a.r - b.r, a.u - b.u, a.v - b.v, a.p - b.p};

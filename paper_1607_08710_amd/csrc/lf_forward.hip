@@ -35,12 +35,6 @@ struct StageArgs {
   int reduce;
 };
 
-// Mass fractions of one row (NS of them; one unused slot when NS = 0).
-template <typename T, int NS>
-struct Frac {
-  T v[NS > 0 ? NS : 1];
-};
-
 template <typename T, int MODE, int BCX, int BCY, int NS, bool CONS>
 __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(StageArgs<T> a) {
   static_assert(!CONS || NS == 0, "the conservative reconstruction is built without mass fractions");

@@ -1,5 +1,5 @@
 // lf_fused.hip -- one whole Heun step (Sec. 5, items 2-11) in a single pass
-// over the state, for states without mass fractions.
+// over the state, mass fractions included.
 //
 // The two-stage path writes the predictor state U* to memory and reads it
 // back (160 B per FP64 cell and step).  Here a wave runs both stages on the
@@ -43,65 +43,116 @@ struct FusedArgs {
   int dt_dev, reduce;
 };
 
-// y-window of one stage: primitive rows a and a+1, the y-slope of row a and
-// the flux through face a-1/2.
-template <typename T>
+// Reconstruction variables of one row: the Euler part (primitive, or
+// conservative under CONS) and the mass fractions y_k = (rho y_k) / rho.
+template <typename T, int NS>
+struct RowV {
+  Prim<T> w;
+  Frac<T, NS> y;
+};
+
+template <bool CONS, int NS, typename T, int NF>
+__device__ __forceinline__ RowV<T, NS> row_vars(const T (&q)[NF], T gm1) {
+  RowV<T, NS> r;
+  r.w = rec_vars<CONS>(q[0], q[1], q[2], q[3], gm1);
+  if constexpr (NS > 0) {
+    const T ir = rcp(q[0]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) r.y.v[s] = q[4 + s] * ir;
+  }
+  return r;
+}
+
+// y-window of one stage: rows a and a+1, the y-slopes of row a and the
+// fluxes through face a-1/2, for the Euler variables and the fractions.
+template <typename T, int NS>
 struct Win {
   Prim<T> w0, w1, s0;
   Flux<T> g;
+  Frac<T, NS> y0, y1, sy0, gy;
 };
 
-// Window of row a from the primitive rows a-2 .. a+1.
-template <bool CONS, typename T>
-__device__ __forceinline__ Win<T> prime_window(const Prim<T>& wa, const Prim<T>& wb, const Prim<T>& w0,
-                                               const Prim<T>& w1, T beta, T gam, T gm1, T igm1) {
-  Win<T> W;
-  const Prim<T> d_mid = sub(w0, wb);
-  const Prim<T> s_b = slope(sub(wb, wa), d_mid, beta);
-  W.s0 = slope(d_mid, sub(w1, w0), beta);
-  W.g = face_flux(face_prim<CONS>(face_plus<T, true>(wb, s_b), gm1),
-                  face_prim<CONS>(face_minus<T, true>(w0, W.s0), gm1), gam, igm1);
-  W.w0 = w0;
-  W.w1 = w1;
+// Window of row a from the rows a-2 .. a+1.
+template <bool CONS, int NS, typename T>
+__device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const RowV<T, NS>& rb,
+                                                   const RowV<T, NS>& r0, const RowV<T, NS>& r1, T beta,
+                                                   T gam, T gm1, T igm1) {
+  Win<T, NS> W;
+  const Prim<T> d_mid = sub(r0.w, rb.w);
+  const Prim<T> s_b = slope(sub(rb.w, ra.w), d_mid, beta);
+  W.s0 = slope(d_mid, sub(r1.w, r0.w), beta);
+  bool gl;
+  W.g = face_flux(face_prim<CONS>(face_plus<T, true>(rb.w, s_b), gm1),
+                  face_prim<CONS>(face_minus<T, true>(r0.w, W.s0), gm1), gam, igm1, gl);
+  W.w0 = r0.w;
+  W.w1 = r1.w;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const T sb = sweby(rb.y.v[s] - ra.y.v[s], r0.y.v[s] - rb.y.v[s], beta);
+    W.sy0.v[s] = sweby(r0.y.v[s] - rb.y.v[s], r1.y.v[s] - r0.y.v[s], beta);
+    W.gy.v[s] = W.g.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? sb : W.sy0.v[s], gl ? rb.y.v[s] : r0.y.v[s]);
+  }
+  W.y0 = r0.y;
+  W.y1 = r1.y;
   return W;
 }
 
 // Residual of eq. (11) for row a of the window (every lane; valid two lanes
-// inside the valid input), given primitive row a+2; slides the window by a
-// row.  Same arithmetic, in the same order, as the stage kernel's row.
-template <bool CONS, typename T>
-__device__ __forceinline__ void window_row(Win<T>& W, const Prim<T>& wn, T beta, T gam, T gm1, T igm1, T kxy,
-                                           T idx, T (&r)[4]) {
-  const Prim<T> s1 = slope(sub(W.w1, W.w0), sub(wn, W.w1), beta);
+// inside the valid input), given row a+2; slides the window by a row.  Same
+// arithmetic, in the same order, as the stage kernel's row, mass fractions
+// included (their face value is one fma on the operands of the upwind side,
+// so no lane shift is left to a branch).
+template <bool CONS, int NS, typename T>
+__device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn, T beta, T gam, T gm1, T igm1,
+                                           T kxy, T idx, T (&r)[4 + NS]) {
+  const Prim<T> s1 = slope(sub(W.w1, W.w0), sub(rn.w, W.w1), beta);
+  bool gl, fl;
   const Flux<T> G = face_flux(face_prim<CONS>(face_plus<T, true>(W.w0, W.s0), gm1),
-                              face_prim<CONS>(face_minus<T, true>(W.w1, s1), gm1), gam, igm1);
+                              face_prim<CONS>(face_minus<T, true>(W.w1, s1), gm1), gam, igm1, gl);
   const Prim<T> wr1 = shl1(W.w0);
   const Prim<T> dxp = sub(wr1, W.w0);
   const Prim<T> dxm = shr1(dxp);
   const Prim<T> sx = slope(dxm, dxp, beta);
   const Prim<T> sx1 = shl1(sx);
   const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(W.w0, sx), gm1),
-                              face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1);
+                              face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1, fl);
   const Flux<T> Fm = shr1(F);
   r[0] = fma(G.f0 - W.g.f0, kxy, F.f0 - Fm.f0) * idx;
   r[1] = fma(G.f2 - W.g.f2, kxy, F.f1 - Fm.f1) * idx;
   r[2] = fma(G.f1 - W.g.f1, kxy, F.f2 - Fm.f2) * idx;
   r[3] = fma(G.f3 - W.g.f3, kxy, F.f3 - Fm.f3) * idx;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const T sy1 = sweby(W.y1.v[s] - W.y0.v[s], rn.y.v[s] - W.y1.v[s], beta);
+    const T gy = G.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? W.sy0.v[s] : sy1, gl ? W.y0.v[s] : W.y1.v[s]);
+    const T yr1 = shl1(W.y0.v[s]);
+    const T dp = yr1 - W.y0.v[s];
+    const T sxs = sweby(shr1(dp), dp, beta);
+    const T sxs1 = shl1(sxs);
+    const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? W.y0.v[s] : yr1);
+    r[4 + s] = fma(gy - W.gy.v[s], kxy, fy - shr1(fy)) * idx;
+    W.sy0.v[s] = sy1;
+    W.gy.v[s] = gy;
+  }
   W.w0 = W.w1;
-  W.w1 = wn;
+  W.w1 = rn.w;
   W.s0 = s1;
   W.g = G;
+  W.y0 = W.y1;
+  W.y1 = rn.y;
 }
 
 // The kernel is bound by arithmetic, not by memory (it moves 64 B per FP64
-// cell and step), so its LDS footprint is kept small for occupancy: U^n of
-// the rows still to be combined waits in a per-wave LDS ring, U* of the two
-// rows waiting for the corrector's combination stays in registers, and one
-// LDS row of U* serves the reads across lanes.  Results are stored straight
-// from the lanes (no staging, no block barrier).
-template <typename T, int BCX, int BCY, bool CONS>
+// cell and step without fractions), so its LDS footprint is kept small for
+// occupancy: U^n of the rows still to be combined waits in a per-wave LDS
+// ring, U* of the two rows waiting for the corrector's combination stays in
+// registers, and one LDS row of U* serves the reads across lanes.  Results
+// are stored straight from the lanes (no staging, no block barrier).
+template <typename T, int BCX, int BCY, int NS, bool CONS>
 __global__ __launch_bounds__(kWave * waves_per_block<T>())
 void fused_step_kernel(FusedArgs<T> a) {
+  static_assert(!CONS || NS == 0, "the conservative reconstruction is built without mass fractions");
+  constexpr int NF = 4 + NS;  // conservative fields: Euler, then rho*y_k
   constexpr int WPB = waves_per_block<T>();
   constexpr bool XT = BCX == kBcTransmissive;
   constexpr bool YT = BCY == kBcTransmissive;
@@ -128,27 +179,23 @@ void fused_step_kernel(FusedArgs<T> a) {
   const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, kxy = a.kxy, idx = a.idx;
 
   const T* __restrict__ I0 = a.in;
-  auto load_row = [&](int row, T (&q)[4]) {
+  auto load_row = [&](int row, T (&q)[NF]) {
     const int off = map_index<BCY>(row, ny) * nx + cm;
-    q[0] = I0[off];
-    q[1] = I0[P + off];
-    q[2] = I0[2 * P + off];
-    q[3] = I0[3 * P + off];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) q[f] = I0[f * P + off];
   };
 
   // U^n ring (rows o .. o+4 are alive while row o is finished) and the
   // U* row exchanged across lanes.
-  __shared__ T nring[WPB][5][4][kWave];
-  __shared__ T srow[WPB][4][kWave];
-  T(*my_n)[4][kWave] = nring[w];
+  __shared__ T nring[WPB][5][NF][kWave];
+  __shared__ T srow[WPB][NF][kWave];
+  T(*my_n)[NF][kWave] = nring[w];
   T(*my_s)[kWave] = srow[w];
   auto nslot = [](int r) { return (r % 5 + 5) % 5; };
-  auto put_n = [&](int r, const T (&q)[4]) {
+  auto put_n = [&](int r, const T (&q)[NF]) {
     const int sl = nslot(r);
-    my_n[sl][0][lane] = q[0];
-    my_n[sl][1][lane] = q[1];
-    my_n[sl][2][lane] = q[2];
-    my_n[sl][3][lane] = q[3];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) my_n[sl][f][lane] = q[f];
   };
   // U* row r as the corrector sees it: transmissive ghost rows are the edge
   // row
@@ -161,10 +208,12 @@ void fused_step_kernel(FusedArgs<T> a) {
   const int nlast = phi + 2;  // last U^n row the predictor reads
 
   // ---- predictor: window of row plo, U^n rows plo+2 and plo+3 in flight ----
-  T QA[4], QB[4] = {T(0), T(0), T(0), T(0)};
-  Win<T> PW;
+  T QA[NF], QB[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) QB[f] = T(0);
+  Win<T, NS> PW;
   {
-    T qa[4], qb[4], q0[4], q1[4];
+    T qa[NF], qb[NF], q0[NF], q1[NF];
     load_row(plo - 2, qa);
     load_row(plo - 1, qb);
     load_row(plo, q0);
@@ -173,61 +222,64 @@ void fused_step_kernel(FusedArgs<T> a) {
     if (plo + 3 <= nlast) load_row(plo + 3, QB);
     put_n(plo, q0);
     put_n(plo + 1, q1);
-    PW = prime_window<CONS>(rec_vars<CONS>(qa[0], qa[1], qa[2], qa[3], gm1),
-                            rec_vars<CONS>(qb[0], qb[1], qb[2], qb[3], gm1),
-                            rec_vars<CONS>(q0[0], q0[1], q0[2], q0[3], gm1),
-                            rec_vars<CONS>(q1[0], q1[1], q1[2], q1[3], gm1), beta, gam, gm1, igm1);
+    PW = prime_window<CONS, NS>(row_vars<CONS, NS>(qa, gm1), row_vars<CONS, NS>(qb, gm1),
+                                row_vars<CONS, NS>(q0, gm1), row_vars<CONS, NS>(q1, gm1), beta, gam, gm1, igm1);
   }
   int pr = plo;  // next U* row to produce
   // U* of the last two rows produced (conservative, this lane's column):
   // S1 = row pr-1, S0 = row pr-2
-  T S0[4] = {T(0), T(0), T(0), T(0)}, S1[4] = {T(0), T(0), T(0), T(0)};
+  T S0[NF], S1[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) S0[f] = S1[f] = T(0);
   // U* row pr = U^n - dt R(U^n); it goes to S1 (S1 moves to S0) and to the
   // LDS row read across lanes
   auto produce = [&]() {
-    const Prim<T> wn = rec_vars<CONS>(QA[0], QA[1], QA[2], QA[3], gm1);  // U^n row pr+2
+    const RowV<T, NS> rn = row_vars<CONS, NS>(QA, gm1);  // U^n row pr+2
     put_n(pr + 2, QA);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) QA[f] = QB[f];
+    for (int f = 0; f < NF; ++f) QA[f] = QB[f];
     if (pr + 4 <= nlast) load_row(pr + 4, QB);
-    T res[4];
-    window_row<CONS>(PW, wn, beta, gam, gm1, igm1, kxy, idx, res);
+    T res[NF];
+    window_row<CONS, NS>(PW, rn, beta, gam, gm1, igm1, kxy, idx, res);
     const int sn = nslot(pr);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NF; ++f) {
       S0[f] = S1[f];
       S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), res[f], dt);
       my_s[f][lane] = S1[f];
     }
     ++pr;
   };
-  // primitive U* of the newest row produced, at this lane's column (ghost
-  // lanes: the edge column)
-  auto star_prim = [&]() {
+  // reconstruction variables of the newest U* row produced, at this lane's
+  // column (ghost lanes: the edge column)
+  auto star_row = [&]() {
+    T q[NF];
     __builtin_amdgcn_wave_barrier();
-    return rec_vars<CONS>(my_s[0][src], my_s[1][src], my_s[2][src], my_s[3][src], gm1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) q[f] = my_s[f][src];
+    return row_vars<CONS, NS>(q, gm1);
   };
 
   // ---- corrector: window of row y0 from U* rows y0-2 .. y0+1 ----
   // Each needed row is read as soon as it is the newest one produced
   // (transmissive ghost rows reuse the edge row).
-  Prim<T> cw[4];
+  RowV<T, NS> cw[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = rmap(y0 - 2 + k);
     while (pr <= r) produce();
-    cw[k] = star_prim();
+    cw[k] = star_row();
   }
-  Win<T> CW = prime_window<CONS>(cw[0], cw[1], cw[2], cw[3], beta, gam, gm1, igm1);
+  Win<T, NS> CW = prime_window<CONS, NS>(cw[0], cw[1], cw[2], cw[3], beta, gam, gm1, igm1);
   // U* (conservative) of the rows the corrector combines next: row o in C0,
   // row o+1 in C1
-  T C0[4], C1[4];
+  T C0[NF], C1[NF];
   {
     // rows y0 and y0+1 were the last ones produced, unless the strip ends
     // at a transmissive top (then row y0 is the newest: y0 == ny - 1)
     const bool two = pr - 1 >= y0 + 1;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NF; ++f) {
       C0[f] = two ? S0[f] : S1[f];
       C1[f] = S1[f];
     }
@@ -240,23 +292,21 @@ void fused_step_kernel(FusedArgs<T> a) {
   for (int o = y0; o < y1; ++o) {
     const bool fresh = o + 2 <= phi;
     if (fresh) produce();
-    const Prim<T> wn = star_prim();  // U* row rmap(o+2), the newest produced
-    T res[4];
-    window_row<CONS>(CW, wn, beta, gam, gm1, igm1, kxy, idx, res);
+    const RowV<T, NS> rn = star_row();  // U* row rmap(o+2), the newest produced
+    T res[NF];
+    window_row<CONS, NS>(CW, rn, beta, gam, gm1, igm1, kxy, idx, res);
     const int sn = nslot(o);
-    T u[4];
+    T u[NF];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], res[f], dt);
+    for (int f = 0; f < NF; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], res[f], dt);
     if (out_lane) {
       const long long so = (long long)o * nx + c;
-      a.out[so] = u[0];
-      a.out[P + so] = u[1];
-      a.out[2 * P + so] = u[2];
-      a.out[3 * P + so] = u[3];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) a.out[f * P + so] = u[f];
     }
     // next row's U*: row o+1 (C1), and row o+2 (just produced, S1) behind it
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NF; ++f) {
       C0[f] = C1[f];
       C1[f] = fresh ? S1[f] : C1[f];
     }
@@ -302,7 +352,7 @@ static int fused_rows(int nx, int ny) {
   return r > ny ? ny : r;
 }
 
-template <typename T, int BCX, int BCY, bool CONS>
+template <typename T, int BCX, int BCY, int NS, bool CONS>
 static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                                  bool reduce, hipStream_t s) {
   constexpr int WPB = waves_per_block<T>();
@@ -329,31 +379,41 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, doubl
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;
-  hipLaunchKernelGGL((fused_step_kernel<T, BCX, BCY, CONS>), dim3(a.blocks_pad), dim3(kWave * WPB), 0, s, a);
+  hipLaunchKernelGGL((fused_step_kernel<T, BCX, BCY, NS, CONS>), dim3(a.blocks_pad), dim3(kWave * WPB), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, bool CONS>
+template <typename T, int BCX, int BCY>
+static hipError_t launch_fused_ns(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
+                                  bool reduce, hipStream_t s) {
+  static_assert(kMaxSpecies == 4, "one instantiation per species count");
+  if (g.recon) return launch_fused_t<T, BCX, BCY, 0, true>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  switch (g.ns) {
+    case 0: return launch_fused_t<T, BCX, BCY, 0, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    case 1: return launch_fused_t<T, BCX, BCY, 1, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    case 2: return launch_fused_t<T, BCX, BCY, 2, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    case 3: return launch_fused_t<T, BCX, BCY, 3, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    default: return launch_fused_t<T, BCX, BCY, 4, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  }
+}
+
+template <typename T>
 static hipError_t launch_fused_bc(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                                   bool reduce, hipStream_t s) {
   if (g.bc_x == kBcPeriodic) {
     if (g.bc_y == kBcPeriodic)
-      return launch_fused_t<T, kBcPeriodic, kBcPeriodic, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    return launch_fused_t<T, kBcPeriodic, kBcTransmissive, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
+      return launch_fused_ns<T, kBcPeriodic, kBcPeriodic>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    return launch_fused_ns<T, kBcPeriodic, kBcTransmissive>(g, in, out, dt, ctl, dt_dev, reduce, s);
   }
   if (g.bc_y == kBcPeriodic)
-    return launch_fused_t<T, kBcTransmissive, kBcPeriodic, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_t<T, kBcTransmissive, kBcTransmissive, CONS>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    return launch_fused_ns<T, kBcTransmissive, kBcPeriodic>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  return launch_fused_ns<T, kBcTransmissive, kBcTransmissive>(g, in, out, dt, ctl, dt_dev, reduce, s);
 }
 
 hipError_t launch_fused_step(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                              bool reduce, hipStream_t s) {
-  if (g.ns != 0) return hipErrorInvalidValue;  // states with mass fractions take the two-stage path
-  if (g.dtype == 0)
-    return g.recon ? launch_fused_bc<double, true>(g, in, out, dt, ctl, dt_dev, reduce, s)
-                   : launch_fused_bc<double, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
-  return g.recon ? launch_fused_bc<float, true>(g, in, out, dt, ctl, dt_dev, reduce, s)
-                 : launch_fused_bc<float, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  if (g.dtype == 0) return launch_fused_bc<double>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  return launch_fused_bc<float>(g, in, out, dt, ctl, dt_dev, reduce, s);
 }
 
 }  // namespace lf

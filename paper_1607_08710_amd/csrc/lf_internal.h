@@ -46,7 +46,7 @@ Layout make_layout(const Grid& g);
 hipError_t launch_stage(const Grid& g, int mode, const void* in, const void* base, void* out,
                         double dt, Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s);
 // One whole Heun step in a single pass, out = step(in); in and out must
-// not overlap; states without mass fractions only.
+// not overlap.
 hipError_t launch_fused_step(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
                              bool reduce, hipStream_t s);
 hipError_t launch_wavespeed(const Grid& g, const void* U, Ctl* ctl, hipStream_t s);

@@ -127,3 +127,21 @@ def test_single_pass_full_size_bitwise():
     S.step(U, out, dt)
     ref = _two_stage(S, U, dt)
     assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("ns", [1, 2, 3, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(1, 1), (9, 1), (57, 33), (225, 40), (449, 66)])
+def test_single_pass_step_bitwise_fractions(shape, bc, dtype, ns):
+    """With mass fractions the single pass carries them through the same
+    window and lane shifts as the stage kernel: bitwise the same."""
+    nx, ny = shape
+    cfg = dict(_cfg(nx, ny, *bc), ns=ns)
+    U = workloads.random_state_fractions(nx, ny, ns, seed=nx * 5 + ny + ns + bc[0] + 2 * bc[1])
+    S = solver_for(cfg, dtype)
+    d = to_dev(U, dtype)
+    dt = S.dt(d)
+    out = S.empty_state()
+    S.step(d, out, dt)
+    assert np.array_equal(to_host(out), to_host(_two_stage(S, d, dt)))

@@ -50,6 +50,6 @@ def test_single_pass_valu_count(tmp_path):
     subprocess.run([_build.hipcc(), *flags, "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
                     "-I", CSRC, "-o", out, os.path.join(CSRC, "lf_fused.hip")], check=True, capture_output=True)
     asm = open(out).read()
-    got = {8: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIdLi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"),
-           4: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIfLi0ELi0ELb0EEEvNS_9FusedArgsIT_EE")}
+    got = {8: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIdLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"),
+           4: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIfLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE")}
     assert got == bench.VALU_OPS_PER_CELL, got
