@@ -18,13 +18,15 @@
 // contributions moved to their cells by DPP shifts; y-faces one per row,
 // with the slot contributions accumulated in a four-row register window.
 // A row is finished when its last y-face (two rows above it) has been
-// processed.  Results go through LDS and are stored as whole 128-byte lines.
+// processed; its results are stored straight from the lanes.
 //
 // Boundaries.  Transmissive: ghost cells copy the edge cell, so the slots
 // that point at ghost cells are folded onto the edge cell; faces beyond the
 // boundary do not exist (their cotangent is zero: g is zero outside).
 // Periodic: the stencil data wrap, faces are indexed in unwrapped
 // coordinates and each (cell, face) pair is visited exactly once.
+#include <stdlib.h>
+
 #include "lf_internal.h"
 
 namespace lf {
@@ -171,11 +173,6 @@ void adjoint_kernel(AdjArgs<T> a) {
     return p4_sel(in, g);
   };
 
-  constexpr int BW = WPB * kAdjTileW;
-  __shared__ T obuf[2][4][BW];
-  const int xb = bx * BW;
-  const int kst = w * kWave + lane;
-  int par = 0;
 
   // window: prim rows k-2 .. k+1, g row k-1, y-accumulators rows k-2 ..
   // k+1 (slots rotate every row).  The slope data of row k-1 are
@@ -274,23 +271,14 @@ void adjoint_kernel(AdjArgs<T> a) {
           res[f] = T(0.5 * double(lam) + double(gg[f]) - a.dt * double(vv[f]));
         }
       }
+      // stored straight from the lanes: the kernel is bound by arithmetic,
+      // and without staging no block barrier ties its waves together
       if (out_lane) {
-        const int kk = w * kAdjTileW + lane - kAdjHalo;
-        obuf[par][0][kk] = res[0];
-        obuf[par][1][kk] = res[1];
-        obuf[par][2][kk] = res[2];
-        obuf[par][3][kk] = res[3];
+        a.out[off] = res[0];
+        a.out[P + off] = res[1];
+        a.out[2 * P + off] = res[2];
+        a.out[3 * P + off] = res[3];
       }
-      __syncthreads();
-      const int col = xb + kst;
-      if (kst < BW && col < nx) {
-        const int so = r * nx + col;
-        a.out[so] = obuf[par][0][kst];
-        a.out[P + so] = obuf[par][1][kst];
-        a.out[2 * P + so] = obuf[par][2][kst];
-        a.out[3 * P + so] = obuf[par][3][kst];
-      }
-      par ^= 1;
     }
     // slide the window
     Wm2 = Wm1;
@@ -322,10 +310,15 @@ static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, con
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.dt = dt;
-  // strip height: 32 rows, halved (to 8) until ~8k waves exist
+  // strip height: 32 rows, halved (to 8) until ~8k waves exist;
+  // LF_ADJ_ROWS (a power of two, 4..4096) overrides it (launch shape only)
   const int tiles_x = (g.nx + kAdjTileW - 1) / kAdjTileW;
   int r = 32;
   while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < 8192) r /= 2;
+  if (const char* env = getenv("LF_ADJ_ROWS")) {
+    const int v = atoi(env);
+    if (v >= 4 && v <= 4096 && (v & (v - 1)) == 0) r = v;
+  }
   if (r > g.ny) r = g.ny;
   a.rows = r;
   const int tiles_y = (g.ny + r - 1) / r;
