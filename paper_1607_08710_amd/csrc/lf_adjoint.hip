@@ -175,10 +175,33 @@ void adjoint_kernel(AdjArgs<T> a) {
 
 
   // window: prim rows k-2 .. k+1, g row k-1, y-accumulators rows k-2 ..
-  // k+1 (slots rotate every row).  The slope data of row k-1 are
-  // recomputed rather than carried, and g of the finished row is read
-  // again (from cache): both keep the FP64 register footprint down.
+  // k+1 (slots rotate every row).  g of the finished row is read again
+  // (from cache).  In FP32 the slope data of row k (value and partials)
+  // are handed to the next iteration, where they are row k-1's, through a
+  // per-wave LDS slot (each lane reads back its own values); in FP64 they
+  // are recomputed instead, since holding them pushes the kernel past 256
+  // registers (measured slower).
+  constexpr bool kCarry = sizeof(T) == 4;
+  __shared__ T scarry[kCarry ? WPB : 1][12][kWave];
+  T(*my_c)[kWave] = scarry[kCarry ? w : 0];
+  auto put_slope = [&](const SlopeD<T>& S) {
+    const T v[12] = {S.s.r, S.s.u, S.s.v, S.s.p, S.da.r, S.da.u, S.da.v, S.da.p,
+                     S.db.r, S.db.u, S.db.v, S.db.p};
+#pragma unroll
+    for (int i = 0; i < 12; ++i) my_c[i][lane] = v[i];
+  };
+  auto get_slope = [&]() {
+    SlopeD<T> S;
+    S.s = {my_c[0][lane], my_c[1][lane], my_c[2][lane], my_c[3][lane]};
+    S.da = {my_c[4][lane], my_c[5][lane], my_c[6][lane], my_c[7][lane]};
+    S.db = {my_c[8][lane], my_c[9][lane], my_c[10][lane], my_c[11][lane]};
+    return S;
+  };
   P4<T> Wm2 = load_u(y0 - 3), Wm1 = load_u(y0 - 2), W0 = load_u(y0 - 1);
+  // slope data of row y0-2 (rows y0-3 .. y0-1)
+  if constexpr (kCarry)
+    put_slope(slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
+                      {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta));
   P4<T> Gm1 = load_g(y0 - 2);
   const P4<T> Z = {T(0), T(0), T(0), T(0)};
   P4<T> Am2 = Z, Am1 = Z, A0 = Z;  // accumulators for rows k-2, k-1, k
@@ -189,9 +212,11 @@ void adjoint_kernel(AdjArgs<T> a) {
     // new data: prim row k+1, g row k
     const P4<T> W1 = load_u(k + 1);
     const P4<T> Gk = load_g(k);
-    // slopes of rows k-1 (rows k-2, k-1, k) and k (rows k-1, k, k+1)
-    const SlopeD<T> Sk1 = slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
-                                  {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta);
+    // slopes of rows k-1 (rows k-2, k-1, k; carried in FP32) and k (rows
+    // k-1, k, k+1)
+    const SlopeD<T> Sk1 = kCarry ? get_slope()
+                                 : slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
+                                           {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta);
     const SlopeD<T> Sk = slope_d({W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p},
                                  {W1.r - W0.r, W1.u - W0.u, W1.v - W0.v, W1.p - W0.p}, beta);
     P4<T> A1 = Z;  // accumulator of row k+1 starts here
@@ -281,6 +306,7 @@ void adjoint_kernel(AdjArgs<T> a) {
       }
     }
     // slide the window
+    if constexpr (kCarry) put_slope(Sk);
     Wm2 = Wm1;
     Wm1 = W0;
     W0 = W1;
