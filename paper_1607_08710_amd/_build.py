@@ -34,11 +34,24 @@ def hipcc() -> str:
 
 
 def build(out: str = SO, extra_flags=()) -> str:
-    tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra_flags,
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
-    subprocess.run(cmd, check=True)
+    """Compile every source to an object in parallel, then link the shared
+    library (the kernels of one file never call into another)."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="lf_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+
+        def compile_one(src_obj):
+            src, obj = src_obj
+            subprocess.run([hipcc(), *compile_flags, *extra_flags, "-I", os.path.join(ROOT, "include"),
+                            "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj], check=True)
+
+        with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as pool:
+            list(pool.map(compile_one, zip(SOURCES, objs)))
+        tmp = out + ".tmp"
+        subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *extra_flags, "-o", tmp, *objs],
+                       check=True)
     os.replace(tmp, out)
     return out
 
