@@ -173,6 +173,60 @@ def forward_leg(L, W, n, dtype_flag, steps, warmup, reps, fractions=0, recon=0):
     return res
 
 
+def four_quadrant_leg(L, W, n, steps):
+    """The four-quadrant Riemann problem at n^2 (transmissive), `steps` steps
+    in FP64 and in FP32 from the same initial state: cell-updates/s of each
+    and the FP32 state's per-field relative L1 / L-infinity error against the
+    FP64 one (the FP64 path itself matches the oracle to 1e-12)."""
+    import torch
+    U64, cfg = W.four_quadrant(n)
+    d64 = torch.from_numpy(U64).cuda()
+    del U64
+    d32 = d64.to(torch.float32)
+    d32_init = d32.clone()
+    res = {"n": n, "steps": steps}
+    dts64 = None
+    for name, flag, d in (("f64", L.LF_F64, d64), ("f32", L.LF_F32, d32)):
+        S = make_solver(L, cfg, flag)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        t, k, dts = S.advance(d, 0.0, math.inf, max_steps=steps, dts_capacity=steps)
+        e1.record()
+        torch.cuda.synchronize()
+        assert k == steps
+        if flag == L.LF_F64:
+            dts64 = dts
+        sec = e0.elapsed_time(e1) / 1e3
+        esz = 8 if flag == L.LF_F64 else 4
+        res[name] = {"value": n * n * steps / sec, "ms_per_step": 1e3 * sec / steps, "t": t,
+                     "single_pass_GBps": BYTES_PER_CELL[("single_pass", esz)] * n * n * steps / sec / 1e9}
+        del S
+    # error of the FP32 path at the FP64 run's times: replay its dt sequence
+    # (untimed) from the same float initial state
+    S = make_solver(L, cfg, L.LF_F32)
+    x, y = d32_init, torch.empty_like(d32_init)
+    for dt in dts64:
+        S.step(x, y, float(dt))
+        x, y = y, x
+    torch.cuda.synchronize()
+    del S, y, d32_init
+    d32 = x
+    a = d32.to(torch.float64)
+    l1, linf = [], []
+    for f in range(4):
+        den1 = d64[f].abs().sum().item() or d64[1].abs().sum().item()
+        deni = d64[f].abs().max().item() or d64[1].abs().max().item()
+        diff = (a[f] - d64[f]).abs()
+        l1.append(diff.sum().item() / den1)
+        linf.append(diff.max().item() / deni)
+    res["fp32_vs_fp64_rel_l1"] = l1
+    res["fp32_vs_fp64_rel_linf"] = linf
+    del a, d32, d64
+    torch.cuda.empty_cache()
+    return res
+
+
 def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
     """Bare lf_adjoint_step rate, and the full gradient (forward + recompute
     + adjoint) of a steps-long rollout with checkpoints every ckpt steps."""
@@ -298,9 +352,11 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="forward,species,adjoint,cpu",
-                    help="comma list of legs to run: forward, species, adjoint, cpu (profiling runs use "
-                         "one leg so that each kernel runs at one grid size)")
+    ap.add_argument("--legs", default="forward,species,quadrant,adjoint,cpu",
+                    help="comma list of legs to run: forward, species, quadrant, adjoint, cpu (profiling "
+                         "runs use one leg so that each kernel runs at one grid size)")
+    ap.add_argument("--quadrant-n", type=int, default=8192)
+    ap.add_argument("--quadrant-steps", type=int, default=1000)
     ap.add_argument("--species-steps", type=int, default=200)
     ap.add_argument("--profile-pass", choices=["none", "kernels"], default="none")
     args = ap.parse_args()
@@ -328,7 +384,7 @@ def main():
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
     f64 = f32 = adj64 = adj32 = roofline = cpu = None
-    species = roofline_two_stage = recon64 = None
+    species = roofline_two_stage = recon64 = quadrant = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
         f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
@@ -375,6 +431,11 @@ def main():
         log(f"FP64 Kelvin-Helmholtz {args.n}^2, conservative-variable reconstruction: {args.species_steps} steps")
         recon64 = forward_leg(L, W, args.n, L.LF_F64, args.species_steps, args.warmup, args.kernel_reps, recon=1)
         log(f"  {recon64['value'] / 1e9:.2f} G cell-updates/s")
+    if "quadrant" in legs:
+        log(f"four-quadrant Riemann problem {args.quadrant_n}^2, {args.quadrant_steps} steps, FP64 and FP32")
+        quadrant = four_quadrant_leg(L, W, args.quadrant_n, args.quadrant_steps)
+        log(f"  FP64 {quadrant['f64']['value'] / 1e9:.2f} G, FP32 {quadrant['f32']['value'] / 1e9:.2f} G "
+            f"cell-updates/s; FP32 vs FP64 rel L1 {max(quadrant['fp32_vs_fp64_rel_l1']):.2e}")
     if "adjoint" in legs:
         log(f"adjoint {args.adj_n}^2, {args.adj_steps} steps, checkpoints every {args.adj_ckpt}")
         adj64 = adjoint_leg(L, W, args.adj_n, L.LF_F64, args.adj_steps, args.adj_ckpt, 10)
@@ -410,6 +471,7 @@ def main():
         "fp32": f32,
         "species": species,
         "conservative_reconstruction": recon64,
+        "four_quadrant": quadrant,
         "adjoint": {"n": args.adj_n, "steps": args.adj_steps, "ckpt_every": args.adj_ckpt,
                     "f64": adj64, "f32": adj32},
         "paper_context": {"value": 81.0e6, "unit": "cell-updates/s",
