@@ -247,6 +247,18 @@ def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
     e1.record()
     torch.cuda.synchronize()
     bare = e0.elapsed_time(e1) / 1e3 / reps
+    # the same adjoint step with the step's U* supplied (as the rollout's
+    # recompute keeps it), i.e. without the predictor pass
+    us = torch.empty_like(U0)
+    S.stage(1, U0, us, dt)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        S.adjoint_step_ustar(U0, us, dt, lam, out)
+    e1.record()
+    torch.cuda.synchronize()
+    bare_us = e0.elapsed_time(e1) / 1e3 / reps
+    del us
     # full gradient of J = 1/2 dx dy sum (rho_N - rho_0)^2 w.r.t. U0
     rho_t = U0[0].clone()
     x = U0.clone().requires_grad_(True)
@@ -263,6 +275,7 @@ def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
         "lf_adjoint_step_per_s": 1.0 / bare,
         "lf_adjoint_step_ms": 1e3 * bare,
         "lf_adjoint_step_GBps": BYTES_PER_CELL[("adjoint_step", esz)] * n * n / bare / 1e9,
+        "lf_adjoint_step_ustar_per_s": 1.0 / bare_us,
         "full_gradient_steps_per_s": steps / full,
         "full_gradient_s": full,
         "grad_finite": bool(torch.isfinite(x.grad).all().item()),

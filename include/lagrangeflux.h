@@ -121,6 +121,15 @@ int lf_dt(lf_ctx *ctx, const void *U, void *ws, void *stream, double *dt_out);
  * bitwise that of lf_stage(1) followed by lf_stage(2). */
 int lf_step(lf_ctx *ctx, const void *Un, void *Unp1, double dt, void *ws, void *stream);
 
+/* lf_step into a separate buffer that also writes the predictor state
+ * U* = U^n - dt R(U^n) of the step (items 2-6) into Ustar, async: for
+ * checkpoint-and-recompute rollouts, which keep U* for
+ * lf_adjoint_step_ustar instead of recomputing it there.  Unp1 is bitwise
+ * that of lf_step and Ustar that of lf_stage(1).  Un, Unp1, Ustar and ws
+ * must not overlap each other (LF_ERR_ARG). */
+int lf_step_save(lf_ctx *ctx, const void *Un, void *Unp1, void *Ustar, double dt, void *ws,
+                 void *stream);
+
 /* One stage of the Heun step at the caller's dt, async (the two kernels
  * lf_step chains, exposed for callers that schedule stages themselves):
  *   stage 1 (predictor, items 2-6):  out = in - dt R(in)
@@ -170,6 +179,13 @@ int lf_residual_vjp(lf_ctx *ctx, const void *U, const void *g, void *out, void *
  * lam_n must not overlap Un or lam_np1. */
 int lf_adjoint_step(lf_ctx *ctx, const void *Un, double dt, const void *lam_np1,
                     void *lam_n, void *ws, void *stream);
+
+/* lf_adjoint_step with the step's predictor state U* supplied by the
+ * caller (as lf_step_save wrote it) instead of recomputed: the same two
+ * adjoint stages, bitwise the same result, one predictor pass less.  Same
+ * context restrictions; lam_n must not overlap Un, Ustar or lam_np1. */
+int lf_adjoint_step_ustar(lf_ctx *ctx, const void *Un, const void *Ustar, double dt,
+                          const void *lam_np1, void *lam_n, void *ws, void *stream);
 
 /* Conservation totals: out[f] = dx*dy * sum_K U_f(K) for the 4 + n_species
  * fields (out has that many entries), summed in FP64 with compensation in

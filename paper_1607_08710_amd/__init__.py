@@ -29,8 +29,9 @@ LF_MAX_SPECIES = 4
 LF_RECON_PRIMITIVE, LF_RECON_CONSERVATIVE = 0, 1
 
 # Names exported by the C ABI (include/lagrangeflux.h).
-ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_stage", "lf_advance",
-                 "lf_residual", "lf_residual_vjp", "lf_adjoint_step", "lf_totals")
+ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_step_save", "lf_stage",
+                 "lf_advance", "lf_residual", "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar",
+                 "lf_totals")
 
 
 class LFError(RuntimeError):
@@ -72,15 +73,17 @@ def lib() -> ctypes.CDLL:
         L.lf_status_string.restype = ctypes.c_char_p
         L.lf_dt.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
         L.lf_step.argtypes = [vp, vp, vp, d, vp, vp]
+        L.lf_step_save.argtypes = [vp, vp, vp, vp, d, vp, vp]
         L.lf_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, d, ctypes.c_int, vp, vp]
         L.lf_advance.argtypes = [vp, vp, d, d, i64, vp, vp, ctypes.POINTER(d), ctypes.POINTER(i64),
                                  ctypes.POINTER(d), i64]
         L.lf_residual.argtypes = [vp, vp, vp, vp, vp]
         L.lf_residual_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lf_adjoint_step.argtypes = [vp, vp, d, vp, vp, vp, vp]
+        L.lf_adjoint_step_ustar.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
         L.lf_totals.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
-        for name in ("lf_init", "lf_dt", "lf_step", "lf_stage", "lf_advance", "lf_residual", "lf_residual_vjp",
-                     "lf_adjoint_step", "lf_totals"):
+        for name in ("lf_init", "lf_dt", "lf_step", "lf_step_save", "lf_stage", "lf_advance", "lf_residual",
+                     "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar", "lf_totals"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -177,6 +180,11 @@ class Solver:
         _check(lib().lf_step(self._ctx, self._arg(Un, "Un"), self._arg(Unp1, "Unp1"), float(dt),
                              ctypes.c_void_p(self.ws.data_ptr()), self._stream()), "lf_step")
 
+    def step_save(self, Un, Unp1, Ustar, dt: float):
+        """One step into Unp1 that also writes the step's predictor state U*."""
+        _check(lib().lf_step_save(self._ctx, self._arg(Un, "Un"), self._arg(Unp1, "Unp1"), self._arg(Ustar, "Ustar"),
+                                  float(dt), ctypes.c_void_p(self.ws.data_ptr()), self._stream()), "lf_step_save")
+
     def stage(self, stage: int, inp, out, dt: float, base=None, reduce: bool = False):
         """One Heun stage: 1 = predictor (out = in - dt R(in)), 2 = corrector
         (out = (base + in - dt R(in))/2)."""
@@ -210,6 +218,13 @@ class Solver:
         _check(lib().lf_adjoint_step(self._ctx, self._arg(Un, "Un"), float(dt), self._arg(lam_np1, "lam_np1"),
                                      self._arg(lam_n, "lam_n"), ctypes.c_void_p(self.ws.data_ptr()),
                                      self._stream()), "lf_adjoint_step")
+
+    def adjoint_step_ustar(self, Un, Ustar, dt: float, lam_np1, lam_n):
+        """lf_adjoint_step with the step's U* given (from step_save)."""
+        _check(lib().lf_adjoint_step_ustar(self._ctx, self._arg(Un, "Un"), self._arg(Ustar, "Ustar"), float(dt),
+                                           self._arg(lam_np1, "lam_np1"), self._arg(lam_n, "lam_n"),
+                                           ctypes.c_void_p(self.ws.data_ptr()), self._stream()),
+               "lf_adjoint_step_ustar")
 
     def totals(self, U) -> np.ndarray:
         out = (ctypes.c_double * self.shape[0])()

@@ -124,12 +124,22 @@ int lf_step(lf_ctx* ctx, const void* Un, void* Unp1, double dt, void* ws, void* 
   // single pass when the output is a separate buffer; in place the two
   // stages, through U* in the workspace
   if (Un != Unp1)
-    return hip_status(lf::launch_fused_step(ctx->g, Un, Unp1, dt, nullptr, false, false, s));
+    return hip_status(lf::launch_fused_step(ctx->g, Un, Unp1, nullptr, dt, nullptr, false, false, s));
   void* us = ustar_of(ctx, ws);
   hipError_t e = lf::launch_stage(ctx->g, lf::kPredictor, Un, nullptr, us, dt, nullptr, false, false, s);
   if (e == hipSuccess)
     e = lf::launch_stage(ctx->g, lf::kCorrector, us, Un, Unp1, dt, nullptr, false, false, s);
   return hip_status(e);
+}
+
+int lf_step_save(lf_ctx* ctx, const void* Un, void* Unp1, void* Ustar, double dt, void* ws, void* stream) {
+  if (!ctx || !Un || !Unp1 || !Ustar || !ws) return LF_ERR_ARG;
+  if (!(dt >= 0.0) || !isfinite(dt)) return LF_ERR_ARG;
+  const size_t n = ctx->state_bytes, w = ctx->L.total;
+  if (overlap(Un, n, Unp1, n) || overlap(Un, n, Ustar, n) || overlap(Unp1, n, Ustar, n)) return LF_ERR_ARG;
+  if (overlap(Un, n, ws, w) || overlap(Unp1, n, ws, w) || overlap(Ustar, n, ws, w)) return LF_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return hip_status(lf::launch_fused_step(ctx->g, Un, Unp1, Ustar, dt, nullptr, false, false, s));
 }
 
 int lf_stage(lf_ctx* ctx, int stage, const void* in, const void* base, void* out, double dt, int reduce,
@@ -184,7 +194,8 @@ int lf_advance(lf_ctx* ctx, void* U, double t0, double t_end, int64_t max_steps,
     if (batch < 1) batch = 1;
     for (long long k = 0; k < batch && e == hipSuccess; ++k) {
       if (fused) {
-        e = lf::launch_fused_step(ctx->g, buf[launched & 1], buf[(launched + 1) & 1], 0.0, ctl, true, true, s);
+        e = lf::launch_fused_step(ctx->g, buf[launched & 1], buf[(launched + 1) & 1], nullptr, 0.0, ctl, true,
+                                  true, s);
         ++launched;
       } else {
         e = lf::launch_stage(ctx->g, lf::kPredictor, U, nullptr, us, 0.0, ctl, true, false, s);
@@ -252,6 +263,21 @@ int lf_adjoint_step(lf_ctx* ctx, const void* Un, double dt, const void* lam_np1,
   void* mu = mu_of(ctx, ws);
   hipError_t e = lf::launch_stage(ctx->g, lf::kPredictor, Un, nullptr, us, dt, nullptr, false, false, s);
   if (e == hipSuccess) e = lf::launch_adjoint(ctx->g, lf::kAdjCorr, us, lam_np1, nullptr, mu, dt, s);
+  if (e == hipSuccess) e = lf::launch_adjoint(ctx->g, lf::kAdjPred, Un, mu, lam_np1, lam_n, dt, s);
+  return hip_status(e);
+}
+
+int lf_adjoint_step_ustar(lf_ctx* ctx, const void* Un, const void* Ustar, double dt, const void* lam_np1,
+                          void* lam_n, void* ws, void* stream) {
+  if (!ctx || !Un || !Ustar || !lam_np1 || !lam_n || !ws || ctx->g.ns != 0 || ctx->g.recon != 0) return LF_ERR_ARG;
+  if (!(dt >= 0.0) || !isfinite(dt)) return LF_ERR_ARG;
+  const size_t n = ctx->state_bytes, w = ctx->L.total;
+  if (overlap(lam_n, n, Un, n) || overlap(lam_n, n, lam_np1, n) || overlap(lam_n, n, Ustar, n)) return LF_ERR_ARG;
+  if (overlap(Un, n, ws, w) || overlap(Ustar, n, ws, w) || overlap(lam_np1, n, ws, w) || overlap(lam_n, n, ws, w))
+    return LF_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* mu = mu_of(ctx, ws);
+  hipError_t e = lf::launch_adjoint(ctx->g, lf::kAdjCorr, Ustar, lam_np1, nullptr, mu, dt, s);
   if (e == hipSuccess) e = lf::launch_adjoint(ctx->g, lf::kAdjPred, Un, mu, lam_np1, lam_n, dt, s);
   return hip_status(e);
 }

@@ -34,6 +34,7 @@ template <typename T>
 struct FusedArgs {
   const T* in;  // U^n
   T* out;       // U^{n+1}, must not overlap in
+  T* ustar;     // nullable: receives the predictor state U* of every cell
   Ctl* ctl;
   int nx, ny, rows;
   int blocks_x, blocks, blocks_pad;
@@ -248,6 +249,13 @@ void fused_step_kernel(FusedArgs<T> a) {
       S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), res[f], dt);
       my_s[f][lane] = S1[f];
     }
+    // U* of the strip's own rows, when asked for (halo rows belong to the
+    // neighbouring strips)
+    if (a.ustar && out_lane && pr >= y0 && pr < y1) {
+      const long long so = (long long)pr * nx + c;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) a.ustar[f * P + so] = S1[f];
+    }
     ++pr;
   };
   // reconstruction variables of the newest U* row produced, at this lane's
@@ -353,12 +361,13 @@ static int fused_rows(int nx, int ny) {
 }
 
 template <typename T, int BCX, int BCY, int NS, bool CONS>
-static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
-                                 bool reduce, hipStream_t s) {
+static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
+                                 bool dt_dev, bool reduce, hipStream_t s) {
   constexpr int WPB = waves_per_block<T>();
   FusedArgs<T> a;
   a.in = static_cast<const T*>(in);
   a.out = static_cast<T*>(out);
+  a.ustar = static_cast<T*>(ustar);
   a.ctl = ctl;
   a.nx = g.nx;
   a.ny = g.ny;
@@ -384,36 +393,36 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, doubl
 }
 
 template <typename T, int BCX, int BCY>
-static hipError_t launch_fused_ns(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
-                                  bool reduce, hipStream_t s) {
+static hipError_t launch_fused_ns(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
+                                  bool dt_dev, bool reduce, hipStream_t s) {
   static_assert(kMaxSpecies == 4, "one instantiation per species count");
-  if (g.recon) return launch_fused_t<T, BCX, BCY, 0, true>(g, in, out, dt, ctl, dt_dev, reduce, s);
+  if (g.recon) return launch_fused_t<T, BCX, BCY, 0, true>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
   switch (g.ns) {
-    case 0: return launch_fused_t<T, BCX, BCY, 0, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    case 1: return launch_fused_t<T, BCX, BCY, 1, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    case 2: return launch_fused_t<T, BCX, BCY, 2, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    case 3: return launch_fused_t<T, BCX, BCY, 3, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    default: return launch_fused_t<T, BCX, BCY, 4, false>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    case 0: return launch_fused_t<T, BCX, BCY, 0, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+    case 1: return launch_fused_t<T, BCX, BCY, 1, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+    case 2: return launch_fused_t<T, BCX, BCY, 2, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+    case 3: return launch_fused_t<T, BCX, BCY, 3, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+    default: return launch_fused_t<T, BCX, BCY, 4, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
   }
 }
 
 template <typename T>
-static hipError_t launch_fused_bc(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
-                                  bool reduce, hipStream_t s) {
+static hipError_t launch_fused_bc(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
+                                  bool dt_dev, bool reduce, hipStream_t s) {
   if (g.bc_x == kBcPeriodic) {
     if (g.bc_y == kBcPeriodic)
-      return launch_fused_ns<T, kBcPeriodic, kBcPeriodic>(g, in, out, dt, ctl, dt_dev, reduce, s);
-    return launch_fused_ns<T, kBcPeriodic, kBcTransmissive>(g, in, out, dt, ctl, dt_dev, reduce, s);
+      return launch_fused_ns<T, kBcPeriodic, kBcPeriodic>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+    return launch_fused_ns<T, kBcPeriodic, kBcTransmissive>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
   }
   if (g.bc_y == kBcPeriodic)
-    return launch_fused_ns<T, kBcTransmissive, kBcPeriodic>(g, in, out, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_ns<T, kBcTransmissive, kBcTransmissive>(g, in, out, dt, ctl, dt_dev, reduce, s);
+    return launch_fused_ns<T, kBcTransmissive, kBcPeriodic>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+  return launch_fused_ns<T, kBcTransmissive, kBcTransmissive>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
 }
 
-hipError_t launch_fused_step(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
-                             bool reduce, hipStream_t s) {
-  if (g.dtype == 0) return launch_fused_bc<double>(g, in, out, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_bc<float>(g, in, out, dt, ctl, dt_dev, reduce, s);
+hipError_t launch_fused_step(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
+                             bool dt_dev, bool reduce, hipStream_t s) {
+  if (g.dtype == 0) return launch_fused_bc<double>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+  return launch_fused_bc<float>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
 }
 
 }  // namespace lf

@@ -46,9 +46,9 @@ Layout make_layout(const Grid& g);
 hipError_t launch_stage(const Grid& g, int mode, const void* in, const void* base, void* out,
                         double dt, Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s);
 // One whole Heun step in a single pass, out = step(in); in and out must
-// not overlap.
-hipError_t launch_fused_step(const Grid& g, const void* in, void* out, double dt, Ctl* ctl, bool dt_dev,
-                             bool reduce, hipStream_t s);
+// not overlap.  ustar (nullable) receives the predictor state U*.
+hipError_t launch_fused_step(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
+                             bool dt_dev, bool reduce, hipStream_t s);
 hipError_t launch_wavespeed(const Grid& g, const void* U, Ctl* ctl, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, double t0, double t_end, long long max_steps, double cfl,
                            hipStream_t s);

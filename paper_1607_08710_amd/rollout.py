@@ -4,11 +4,14 @@ checkpoint-and-recompute over the time steps.
 Forward: N calls of ``lf_step`` with the given dts; the state at every
 ``ckpt_every``-th step is kept (those are the outputs of the step calls,
 not copies).  Backward: for each segment, last to first, the segment's
-states are recomputed from its checkpoint with ``lf_step`` and the adjoint
-is carried back through it with ``lf_adjoint_step`` (the discrete adjoint
-of the step map, recomputing U* from U^n inside the library).
+states are recomputed from its checkpoint with ``lf_step_save``, which
+also keeps each step's predictor state U* (the last step of the segment
+needs only its predictor stage), and the adjoint is carried back through
+the segment with ``lf_adjoint_step_ustar`` (the discrete adjoint of the
+step map at that U*).
 
-Peak device memory: the checkpoints plus one segment of states.
+Peak device memory: the checkpoints plus one segment of states and of
+predictor states.
 """
 from __future__ import annotations
 
@@ -58,14 +61,19 @@ class LagrangeFluxRollout(torch.autograd.Function):
             n0 = s * C
             n1 = min(N, n0 + C)
             states = [ckpts[s]]
+            ustars = []
             for n in range(n0, n1 - 1):
-                out = solver.empty_state()
-                solver.step(states[-1], out, dts[n])
+                out, us = solver.empty_state(), solver.empty_state()
+                solver.step_save(states[-1], out, us, dts[n])
                 states.append(out)
+                ustars.append(us)
+            us = solver.empty_state()
+            solver.stage(1, states[-1], us, dts[n1 - 1])
+            ustars.append(us)
             for n in reversed(range(n0, n1)):
-                solver.adjoint_step(states[n - n0], dts[n], lam, lam_next)
+                solver.adjoint_step_ustar(states[n - n0], ustars[n - n0], dts[n], lam, lam_next)
                 lam, lam_next = lam_next, lam
-            del states
+            del states, ustars
         return lam, None, None, None
 
 

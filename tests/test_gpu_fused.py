@@ -145,3 +145,29 @@ def test_single_pass_step_bitwise_fractions(shape, bc, dtype, ns):
     out = S.empty_state()
     S.step(d, out, dt)
     assert np.array_equal(to_host(out), to_host(_two_stage(S, d, dt)))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(1, 1), (9, 1), (57, 33), (225, 40)])
+def test_step_save_and_adjoint_ustar_bitwise(shape, bc, dtype):
+    """lf_step_save writes lf_step's U^{n+1} and lf_stage(1)'s U*, and
+    lf_adjoint_step_ustar on that U* gives lf_adjoint_step's result."""
+    import torch
+    nx, ny = shape
+    cfg = _cfg(nx, ny, *bc)
+    U = workloads.random_state(nx, ny, seed=nx + 3 * ny + bc[0])
+    S = solver_for(cfg, dtype)
+    d = to_dev(U, dtype)
+    dt = S.dt(d)
+    out, us = S.empty_state(), S.empty_state()
+    S.step_save(d, out, us, dt)
+    ref_out, ref_us = S.empty_state(), S.empty_state()
+    S.step(d, ref_out, dt)
+    S.stage(1, d, ref_us, dt)
+    assert torch.equal(out, ref_out) and torch.equal(us, ref_us)
+    lam = to_dev(np.random.default_rng(3).standard_normal(U.shape), dtype)
+    a, b = S.empty_state(), S.empty_state()
+    S.adjoint_step(d, dt, lam, a)
+    S.adjoint_step_ustar(d, us, dt, lam, b)
+    assert torch.equal(a, b)

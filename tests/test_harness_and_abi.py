@@ -113,6 +113,13 @@ def test_entry_points_validate_before_hip():
     assert lib.lf_adjoint_step(ctx, A, 0.1, B, A, W, None) == E
     assert lib.lf_adjoint_step(ctx, A, -0.1, B, vp(0x800000), W, None) == E
     assert lib.lf_totals(ctx, A, W, None, None) == E
+    C = vp(0x700000)
+    assert lib.lf_step_save(ctx, A, B, None, 0.1, W, None) == E
+    assert lib.lf_step_save(ctx, A, B, A, 0.1, W, None) == E          # U* overlaps Un
+    assert lib.lf_step_save(ctx, A, B, C, -1.0, W, None) == E
+    assert lib.lf_step_save(ctx, A, A, C, 0.1, W, None) == E          # no in-place form
+    assert lib.lf_adjoint_step_ustar(ctx, A, B, 0.1, C, B, W, None) == E  # lam_n overlaps U*
+    assert lib.lf_adjoint_step_ustar(ctx, A, None, 0.1, C, B, W, None) == E
     lib.lf_destroy(ctx)
 
 
