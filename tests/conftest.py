@@ -39,3 +39,28 @@ def read_golden(name):
             if line and not line.startswith("#"):
                 rows.append(line.split())
     return rows
+
+
+@pytest.fixture(scope="session")
+def kernel_asm(tmp_path_factory):
+    """gfx950 assembly of each HIP source of the library, compiled once per
+    session (in parallel) for the tests that inspect the generated code."""
+    import subprocess
+    from concurrent.futures import ThreadPoolExecutor
+    if not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc not installed")
+    from paper_1607_08710_amd import _build
+    tmp = tmp_path_factory.mktemp("asm")
+    flags = [f for f in _build.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    srcs = ["lf_forward.hip", "lf_fused.hip", "lf_adjoint.hip"]
+
+    def one(src):
+        out = str(tmp / (src + ".s"))
+        subprocess.run([_build.hipcc(), *flags, "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
+                        "-I", _build.CSRC, "-o", out, os.path.join(_build.CSRC, src)],
+                       check=True, capture_output=True)
+        with open(out) as fh:
+            return src, fh.read()
+
+    with ThreadPoolExecutor(max_workers=len(srcs)) as pool:
+        return dict(pool.map(one, srcs))

@@ -9,24 +9,9 @@ select into a branch and moving a shift into one arm), so this test
 compiles the kernels for gfx950 to assembly and checks that no DPP
 instruction lies between an EXEC-narrowing instruction and the
 restoring one."""
-import os
 import re
-import subprocess
 
 import pytest
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_1607_08710_amd", "csrc")
-
-
-def _assembly(src, tmp_path):
-    from paper_1607_08710_amd import _build
-    out = str(tmp_path / (src + ".s"))
-    flags = [f for f in _build.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
-    cmd = [_build.hipcc(), *flags, "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
-           "-I", CSRC, "-o", out, os.path.join(CSRC, src)]
-    subprocess.run(cmd, check=True, capture_output=True)
-    return open(out).read()
 
 
 def _shifts_in_divergent_code(asm):
@@ -49,9 +34,7 @@ def _shifts_in_divergent_code(asm):
 
 
 @pytest.mark.parametrize("src", ["lf_forward.hip", "lf_fused.hip", "lf_adjoint.hip"])
-def test_no_lane_shift_in_divergent_code(src, tmp_path):
-    if not os.path.exists("/opt/rocm/bin/hipcc"):
-        pytest.skip("hipcc not installed")
-    asm = _assembly(src, tmp_path)
+def test_no_lane_shift_in_divergent_code(src, kernel_asm):
+    asm = kernel_asm[src]
     assert "_dpp" in asm  # the kernels do use lane shifts
     assert _shifts_in_divergent_code(asm) == {}

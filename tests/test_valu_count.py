@@ -5,13 +5,9 @@ per cell) takes in the gfx950 assembly.  This test recounts that number from a f
 the figure the benchmark reports cannot drift from the kernel."""
 import os
 import re
-import subprocess
 import sys
 
-import pytest
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_1607_08710_amd", "csrc")
 
 
 def _main_loop_valu(asm, symbol):
@@ -39,17 +35,10 @@ def _main_loop_valu(asm, symbol):
     return sum(1 for x in body if x.startswith("v_"))
 
 
-def test_single_pass_valu_count(tmp_path):
-    if not os.path.exists("/opt/rocm/bin/hipcc"):
-        pytest.skip("hipcc not installed")
-    from paper_1607_08710_amd import _build
+def test_single_pass_valu_count(kernel_asm):
     sys.path.insert(0, ROOT)
     import bench
-    out = str(tmp_path / "fused.s")
-    flags = [f for f in _build.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
-    subprocess.run([_build.hipcc(), *flags, "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
-                    "-I", CSRC, "-o", out, os.path.join(CSRC, "lf_fused.hip")], check=True, capture_output=True)
-    asm = open(out).read()
+    asm = kernel_asm["lf_fused.hip"]
     got = {8: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIdLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"),
            4: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIfLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE")}
     assert got == bench.VALU_OPS_PER_CELL, got
