@@ -41,7 +41,11 @@ class LFError(RuntimeError):
 
 
 class NonPhysicalState(LFError):
-    pass
+    """A state with rho <= 0, p <= 0 or a non-finite value was met.  From
+    Solver.advance, ``t`` and ``steps`` tell how far the run got (the state
+    produced by the last step is left in U)."""
+    t = None
+    steps = None
 
 
 class lf_params(ctypes.Structure):
@@ -202,6 +206,10 @@ class Solver:
         rc = lib().lf_advance(self._ctx, self._arg(U, "U"), float(t0), float(t_end), int(max_steps),
                               ctypes.c_void_p(self.ws.data_ptr()), self._stream(), ctypes.byref(t),
                               ctypes.byref(n), dptr, int(dts_capacity))
+        if rc == LF_ERR_NONPHYSICAL:
+            e = NonPhysicalState("lf_advance", rc)
+            e.t, e.steps = t.value, n.value
+            raise e
         _check(rc, "lf_advance")
         return t.value, n.value, (dts[: min(n.value, dts_capacity)].copy() if dts_capacity else None)
 

@@ -88,13 +88,16 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
   const T* B2 = B1 + plane;
   const T* B3 = B2 + plane;
   const T* BS = B3 + plane;
+  // U^n of the corrector is read once and the output written once: both
+  // go as streaming (non-temporal) accesses, leaving the caches to the
+  // stencil rows that neighbouring tiles re-read
   auto load_base = [&](int off, T (&b)[NF]) {
-    b[0] = B0[off];
-    b[1] = B1[off];
-    b[2] = B2[off];
-    b[3] = B3[off];
+    b[0] = __builtin_nontemporal_load(&B0[off]);
+    b[1] = __builtin_nontemporal_load(&B1[off]);
+    b[2] = __builtin_nontemporal_load(&B2[off]);
+    b[3] = __builtin_nontemporal_load(&B3[off]);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) b[4 + s] = BS[s * plane + off];
+    for (int s = 0; s < NS; ++s) b[4 + s] = __builtin_nontemporal_load(&BS[s * plane + off]);
   };
 
   // Row pipeline.  While row o is finished, the stencil rows o+3 and o+4
@@ -265,12 +268,12 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       const int col = xb + kst;
       if (kst < BW && col < nx) {
         const int so = o * nx + col;
-        O0[so] = obuf[par][0][kst];
-        O1[so] = obuf[par][1][kst];
-        O2[so] = obuf[par][2][kst];
-        O3[so] = obuf[par][3][kst];
+        __builtin_nontemporal_store(obuf[par][0][kst], &O0[so]);
+        __builtin_nontemporal_store(obuf[par][1][kst], &O1[so]);
+        __builtin_nontemporal_store(obuf[par][2][kst], &O2[so]);
+        __builtin_nontemporal_store(obuf[par][3][kst], &O3[so]);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) OS[s * plane + so] = obuf[par][4 + s][kst];
+        for (int s = 0; s < NS; ++s) __builtin_nontemporal_store(obuf[par][4 + s][kst], &OS[s * plane + so]);
       }
       par ^= 1;
     }
