@@ -12,9 +12,12 @@ Prints ONE JSON line on stdout: the FP64 cell-updates/s as ``value``; the
 roofline of the dominant kernel (the single-pass step, bound by VALU issue)
 and of the two-stage design's corrector against HBM, each from HIP events
 on the stream the kernel runs on; the FP32 path, the two-stage path, the
-mass-fraction runs and the adjoint (lf_adjoint_step and the checkpointed
-full gradient at 4096^2) as extra objects; and the FP64 CPU oracle timed on
-a bounded sample on this host.
+mass-fraction runs, the four-quadrant problem at 8192^2, the isentropic
+vortex at 4096^2 (rate and error against the exact solution) and the
+adjoint (lf_adjoint_step and the checkpointed full gradient at 4096^2) as
+extra objects; a plain device copy's bandwidth beside the rooflines; and
+the FP64 CPU oracle timed on a bounded sample on this host (all threads,
+and one thread).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
   python bench.py --profile-pass kernels   # short fixed sequence for rocprofv3
@@ -43,12 +46,12 @@ BYTES_PER_CELL = {               # algorithmic (compulsory) bytes per cell
     ("single_pass", 8): 64, ("single_pass", 4): 32,
     ("adjoint_step", 8): 288, ("adjoint_step", 4): 144,
 }
-# VALU instructions per cell and step of the single-pass kernel: one
-# iteration of its main loop (a predictor row, a corrector row and the CFL
-# reduction, per lane) in the gfx950 assembly of fused_step_kernel<T,
-# periodic, periodic>; tests/test_valu_count.py recounts it from a fresh
-# build.
-VALU_OPS_PER_CELL = {8: 681, 4: 577}
+# VALU instructions per cell and step of the single-pass kernel: its main
+# loop's trip of three rows (each a predictor row, a corrector row and the
+# CFL reduction, per lane) in the gfx950 assembly of fused_step_kernel<T,
+# periodic, periodic, no fractions>, divided by 3; tests/test_valu_count.py
+# recounts it from a fresh build.
+VALU_OPS_PER_CELL = {8: 1918 / 3, 4: 1606 / 3}
 KERNEL_SOURCES = ["paper_1607_08710_amd/csrc/lf_forward.hip", "paper_1607_08710_amd/csrc/lf_fused.hip",
                   "paper_1607_08710_amd/csrc/lf_device.h", "paper_1607_08710_amd/csrc/lf_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kh16384.json")
@@ -227,6 +230,58 @@ def four_quadrant_leg(L, W, n, steps):
     return res
 
 
+def vortex_leg(L, W, n, t_end=2.0):
+    """The isentropic vortex (periodic [0,10]^2, advected by (1, 1)) at n^2
+    up to t_end, in FP64 and in FP32 from the same initial state: the
+    cell-updates/s of each lf_advance run (dt on the device) and the L1
+    error of the density against the exact solution, the initial vortex
+    translated by (t_end, t_end)."""
+    import torch
+    U, cfg = W.vortex(n, t_end=t_end)
+    exact, _ = W.vortex(n, t=t_end)
+    rho_exact = torch.from_numpy(exact[0]).cuda()
+    del exact
+    res = {"n": n, "t_end": t_end}
+    for name, flag, tdt in (("f64", L.LF_F64, torch.float64), ("f32", L.LF_F32, torch.float32)):
+        d = torch.from_numpy(U).to(device="cuda", dtype=tdt)
+        S = make_solver(L, cfg, flag)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        t, k, _ = S.advance(d, 0.0, t_end)
+        e1.record()
+        torch.cuda.synchronize()
+        assert t == t_end, (t, t_end)
+        sec = e0.elapsed_time(e1) / 1e3
+        err = (d[0].to(torch.float64) - rho_exact).abs().mean().item()
+        res[name] = {"value": n * n * k / sec, "steps": k, "ms_per_step": 1e3 * sec / k, "rho_l1_error": err}
+        del d, S
+    del rho_exact
+    torch.cuda.empty_cache()
+    return res
+
+
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """HBM bandwidth of a plain device-to-device copy (torch's copy kernel),
+    bytes read + written per second: what a streaming kernel reaches on
+    this GPU, next to the nominal 8 TB/s."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
+
+
 def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
     """Bare lf_adjoint_step rate, and the full gradient (forward + recompute
     + adjoint) of a steps-long rollout with checkpoints every ckpt steps."""
@@ -305,6 +360,18 @@ def cpu_baseline(W, n=2048, min_seconds=10.0, max_steps=400):
                       f"OMP_NUM_THREADS={cores}"}
 
 
+def cpu_per_core(n=1024, min_seconds=4.0):
+    """The oracle on one thread (the per-core figure the paper compares
+    with), in a child process started with OMP_NUM_THREADS=1 (OpenMP reads
+    it at start-up); the child touches no GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-only", "--cpu-n", str(n),
+                          "--cpu-seconds", str(min_seconds)], env=env, capture_output=True, text=True,
+                         timeout=600, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
 def traffic_entry(n, key):
     """HBM bytes per launch of one kernel (key in the counter record, e.g.
     corrector_f64_bytes) from the committed rocprofv3 counter summary, or
@@ -365,14 +432,22 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="forward,species,quadrant,adjoint,cpu",
-                    help="comma list of legs to run: forward, species, quadrant, adjoint, cpu (profiling "
-                         "runs use one leg so that each kernel runs at one grid size)")
+    ap.add_argument("--legs", default="forward,species,quadrant,vortex,adjoint,cpu",
+                    help="comma list of legs to run: forward, species, quadrant, vortex, adjoint, cpu "
+                         "(profiling runs use one leg so that each kernel runs at one grid size)")
+    ap.add_argument("--vortex-n", type=int, default=4096)
+    ap.add_argument("--cpu-n", type=int, default=2048, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--quadrant-n", type=int, default=8192)
     ap.add_argument("--quadrant-steps", type=int, default=1000)
     ap.add_argument("--species-steps", type=int, default=200)
     ap.add_argument("--profile-pass", choices=["none", "kernels"], default="none")
     args = ap.parse_args()
+
+    if args.oracle_only:  # child of cpu_per_core(): the oracle alone, no GPU
+        import workloads as W
+        print(json.dumps(cpu_baseline(W, n=args.cpu_n, min_seconds=args.cpu_seconds)), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -397,7 +472,7 @@ def main():
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
     f64 = f32 = adj64 = adj32 = roofline = cpu = None
-    species = roofline_two_stage = recon64 = quadrant = None
+    species = roofline_two_stage = recon64 = quadrant = vortex = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
         f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
@@ -414,23 +489,29 @@ def main():
         sp_s = f64["ms_per_step"] / 1e3
         achieved = VALU_OPS_PER_CELL[8] * cells / sp_s / 1e12
         traffic, traffic_src = traffic_entry(args.n, "single_pass_f64_bytes")
-        roofline = {"bound": "alu", "kernel": "lf::fused_step_kernel<double, 0, 0> (FP64 single-pass step, periodic)",
+        copy_gbps = copy_bandwidth()
+        log(f"device copy {copy_gbps:.0f} GB/s")
+        roofline = {"bound": "alu",
+                    "kernel": "lf::fused_step_kernel<double, 0, 0, 0, false> (FP64 single-pass step, periodic)",
                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_source": traffic_src,
                     "algorithmic_ops_per_cell": VALU_OPS_PER_CELL[8],
                     "ops": "VALU lane-instructions per cell-step, counted from the kernel's gfx950 assembly",
                     "algorithmic_bytes_per_cell": BYTES_PER_CELL[("single_pass", 8)],
                     "hbm_GBps": BYTES_PER_CELL[("single_pass", 8)] * cells / sp_s / 1e9,
-                    "cells_per_launch": cells, "avg_launch_ms": f64["ms_per_step"]}
+                    "cells_per_launch": cells, "avg_launch_ms": f64["ms_per_step"],
+                    "measured_copy_GBps": copy_gbps}
         # the two-stage design (one kernel per stage) against HBM
         corr_s = f64["corrector_ms"] / 1e3
         ach2 = BYTES_PER_CELL[("corrector", 8)] * cells / corr_s / 1e9
         traffic2, traffic_src2 = traffic_entry(args.n, "corrector_f64_bytes")
-        roofline_two_stage = {"bound": "hbm", "kernel": "lf::stage_kernel<double, 2, 0, 0, 0> (FP64 corrector, periodic)",
+        roofline_two_stage = {"bound": "hbm",
+                              "kernel": "lf::stage_kernel<double, 2, 0, 0, 0, false> (FP64 corrector, periodic)",
                               "achieved": ach2, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                               "frac": ach2 / HBM_PEAK_GBPS, "traffic": traffic2, "traffic_source": traffic_src2,
                               "algorithmic_bytes_per_cell": BYTES_PER_CELL[("corrector", 8)],
-                              "cells_per_launch": cells, "avg_launch_ms": f64["corrector_ms"]}
+                              "cells_per_launch": cells, "avg_launch_ms": f64["corrector_ms"],
+                              "measured_copy_GBps": copy_gbps, "frac_of_measured_copy": ach2 / copy_gbps}
     if "species" in legs:
         species = {}
         for k in (1, 2):
@@ -449,6 +530,12 @@ def main():
         quadrant = four_quadrant_leg(L, W, args.quadrant_n, args.quadrant_steps)
         log(f"  FP64 {quadrant['f64']['value'] / 1e9:.2f} G, FP32 {quadrant['f32']['value'] / 1e9:.2f} G "
             f"cell-updates/s; FP32 vs FP64 rel L1 {max(quadrant['fp32_vs_fp64_rel_l1']):.2e}")
+    if "vortex" in legs:
+        log(f"isentropic vortex {args.vortex_n}^2 to t = 2, FP64 and FP32")
+        vortex = vortex_leg(L, W, args.vortex_n)
+        log(f"  FP64 {vortex['f64']['value'] / 1e9:.2f} G cell-updates/s over {vortex['f64']['steps']} steps, "
+            f"rho L1 error {vortex['f64']['rho_l1_error']:.3e}; FP32 {vortex['f32']['value'] / 1e9:.2f} G, "
+            f"{vortex['f32']['rho_l1_error']:.3e}")
     if "adjoint" in legs:
         log(f"adjoint {args.adj_n}^2, {args.adj_steps} steps, checkpoints every {args.adj_ckpt}")
         adj64 = adjoint_leg(L, W, args.adj_n, L.LF_F64, args.adj_steps, args.adj_ckpt, 10)
@@ -460,6 +547,8 @@ def main():
         log("CPU oracle baseline")
         cpu = cpu_baseline(W, min_seconds=args.cpu_seconds)
         log(f"oracle {cpu['value'] / 1e6:.2f} M cell-updates/s on {cpu['cores']} threads")
+        cpu["one_thread"] = cpu_per_core()
+        log(f"oracle on one thread {cpu['one_thread']['value'] / 1e6:.2f} M cell-updates/s")
 
     line = {
         "metric": METRIC,
@@ -485,6 +574,7 @@ def main():
         "species": species,
         "conservative_reconstruction": recon64,
         "four_quadrant": quadrant,
+        "vortex": vortex,
         "adjoint": {"n": args.adj_n, "steps": args.adj_steps, "ckpt_every": args.adj_ckpt,
                     "f64": adj64, "f32": adj32},
         "paper_context": {"value": 81.0e6, "unit": "cell-updates/s",

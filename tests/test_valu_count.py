@@ -1,8 +1,9 @@
 """The single-pass step kernel is bound by VALU issue, and bench.py prices
-it with the number of VALU instructions one iteration of its main loop
-(a predictor row and a corrector row with the CFL reduction, per lane =
-per cell) takes in the gfx950 assembly.  This test recounts that number from a fresh compile, so
-the figure the benchmark reports cannot drift from the kernel."""
+it with the number of VALU instructions its main loop takes per row (a
+predictor row and a corrector row with the CFL reduction, per lane = per
+cell) in the gfx950 assembly.  The loop runs three rows per trip; this
+test recounts the trip from a fresh compile, so the figure the benchmark
+reports cannot drift from the kernel."""
 import os
 import re
 import sys
@@ -32,7 +33,11 @@ def _main_loop_valu(asm, symbol):
     assert body, loops
     body = max(body, key=len)
     assert any(x.startswith("v_rsq") for x in body)  # the reduction's sound speed is in it
-    return sum(1 for x in body if x.startswith("v_"))
+    # rows per trip: each row stores the four fields of U^{n+1} and of the
+    # optional U*
+    stores = sum(1 for x in body if x.startswith("global_store"))
+    assert stores % 8 == 0, stores
+    return sum(1 for x in body if x.startswith("v_")) / (stores // 8)
 
 
 def test_single_pass_valu_count(kernel_asm):
