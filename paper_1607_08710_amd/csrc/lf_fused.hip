@@ -337,13 +337,18 @@ void fused_step_kernel(FusedArgs<T> a) {
   // with three bodies per trip every loop-carried value is last read before
   // its successor is written, and the register rotation costs no moves
   // (about 6% of the loop's instructions).  The compiler does not unroll
-  // this loop itself: it holds cross-lane operations.
+  // this loop itself: it holds cross-lane operations.  FP64 with two or
+  // more fractions keeps one row per trip: unrolled, it would need more
+  // than 256 VGPRs, i.e. one wave per SIMD.
+  constexpr bool kThreeRows = !(sizeof(T) == 8 && NS >= 2);
   int o = y0;
+  if constexpr (kThreeRows) {
 #pragma unroll 1
-  for (; o + 3 <= y1; o += 3) {
-    row(o);
-    row(o + 1);
-    row(o + 2);
+    for (; o + 3 <= y1; o += 3) {
+      row(o);
+      row(o + 1);
+      row(o + 2);
+    }
   }
 #pragma unroll 1
   for (; o < y1; ++o) row(o);
