@@ -363,14 +363,14 @@ void fused_step_kernel(FusedArgs<T> a) {
   }
 }
 
-// Strip height of the fused kernel: 64 rows (each strip recomputes 4 rows
-// of U* for its halo; measured on MI355X at 16384^2, 64 and 128 rows are
-// best in FP64, 64 in FP32), halved (down to 8) until at least ~8k waves
-// exist; LF_FUSED_ROWS (a power of two, 4..4096) overrides it.  The launch
-// shape never changes the result.
-static int fused_rows(int nx, int ny) {
+// Strip height of the fused kernel: 128 rows in FP64, 64 in FP32 (each
+// strip recomputes 4 rows of U* for its halo; measured best on MI355X at
+// 16384^2), halved (down to 8) until at least ~8k waves exist;
+// LF_FUSED_ROWS (a power of two, 4..4096) overrides it.  The launch shape
+// never changes the result.
+static int fused_rows(int nx, int ny, int esize) {
   const int tiles_x = (nx + kFTileW - 1) / kFTileW;
-  int r = 64;
+  int r = esize == 8 ? 128 : 64;
   while (r > 8 && (long long)tiles_x * ((ny + r - 1) / r) < 8192) r /= 2;
   if (const char* env = getenv("LF_FUSED_ROWS")) {
     const int v = atoi(env);
@@ -390,7 +390,7 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void*
   a.ctl = ctl;
   a.nx = g.nx;
   a.ny = g.ny;
-  a.rows = fused_rows(g.nx, g.ny);
+  a.rows = fused_rows(g.nx, g.ny, (int)sizeof(T));
   const int tiles_x = (g.nx + kFTileW - 1) / kFTileW;
   const int tiles_y = (g.ny + a.rows - 1) / a.rows;
   a.blocks_x = (tiles_x + WPB - 1) / WPB;
