@@ -152,13 +152,15 @@ __device__ __forceinline__ Prim<T> rec_vars(T q0, T q1, T q2, T q3, T gm1) {
 // library accepts beta = 0 or 1 <= beta <= 2.  With bs = b sign(a), a
 // negative bs (ab < 0) makes the result negative before the max with 0,
 // so one expression also covers the ab <= 0 branch.  The result carries
-// the sign of a.
+// the sign of a.  In FP32, max(0, min(lo, hi)) is the median of (0, lo,
+// hi), one instruction, since hi = max(|a|, bs) is never negative.
 template <typename T>
 __device__ __forceinline__ T sweby(T a, T b, T beta) {
   const T bs = copysign(T(1), a) * b;
   const T aa = fabs(a);
-  const T m = fmin(beta * fmin(aa, bs), fmax(aa, bs));
-  return copysign(fmax(m, T(0)), a);
+  const T lo = beta * fmin(aa, bs), hi = fmax(aa, bs);
+  if constexpr (sizeof(T) == 4) return copysign(__builtin_amdgcn_fmed3f(0.0f, lo, hi), a);
+  else return copysign(fmax(fmin(lo, hi), T(0)), a);
 }
 
 // Value and partial derivatives of eq. (sweby) in one pass, with the
