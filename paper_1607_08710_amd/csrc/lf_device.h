@@ -373,16 +373,19 @@ __device__ __forceinline__ Flux<T> shr1(const Flux<T>& f) {
   return {shr1(f.f0), shr1(f.f1), shr1(f.f2), shr1(f.f3)};
 }
 
-// Combination of one stage in FP64: predictor U - dt R; corrector
-// (U^n + U* - dt R(U*)) / 2; residual mode writes R.
+// Combination of one stage, formed in FP64 from the cell's flux balance
+// s = (F_{i+1/2} - F_{i-1/2}) + (dx/dy) (G_{j+1/2} - G_{j-1/2}), of which
+// the residual of eq. (11) is R = s / dx: predictor U - dt R = U - dtx s;
+// corrector (U^n + U* - dtx s(U*)) / 2, with dtx = dt / dx; the residual
+// mode writes s / dx in T.
 template <int MODE, typename T>
-__device__ __forceinline__ T combine(T q, T b, T res, double dt) {
+__device__ __forceinline__ T combine(T q, T b, T s, double dtx, T idx) {
   if constexpr (MODE == kResidual) {
-    return res;
+    return s * idx;
   } else if constexpr (MODE == kPredictor) {
-    return T(double(q) - dt * double(res));
+    return T(fma(-dtx, double(s), double(q)));
   } else {
-    return T(0.5 * (double(b) + (double(q) - dt * double(res))));
+    return T(0.5 * (double(b) + fma(-dtx, double(s), double(q))));
   }
 }
 

@@ -30,6 +30,7 @@ struct StageArgs {
   int blocks_x, blocks, blocks_pad;
   long long plane;
   T gamma, gm1, inv_gm1, beta, idx, idy, kxy;  // kxy = dx / dy
+  double rdx;  // 1 / dx, for dt / dx
   double dt;
   int dt_dev;
   int reduce;
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
   const int y1 = min(y0 + a.rows, a.ny);
   const bool out_lane = lane >= kHalo && lane < kWave - kHalo && c < a.nx;
   const double dt = a.dt_dev ? a.ctl->dt : a.dt;
+  const double dtx = dt * a.rdx;
   const int nx = a.nx, ny = a.ny;
   const long long plane = a.plane;
   const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta;
@@ -216,12 +218,13 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const Flux<T> Fm = shr1(F);         // flux through face c-1/2
 
     // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11),
-    // formed as (dF + dG (dx/dy)) / dx: with square cells dx/dy = 1 and the
+    // as the flux balance s = dF + dG (dx/dy) with R = s / dx (the stage
+    // combination takes dt / dx): with square cells dx/dy = 1 and the
     // single rounding of dF + dG keeps the x/y mirror symmetry exact.
-    const T r0 = fma(G.f0 - Gp.f0, a.kxy, F.f0 - Fm.f0) * a.idx;
-    const T r1 = fma(G.f2 - Gp.f2, a.kxy, F.f1 - Fm.f1) * a.idx;
-    const T r2 = fma(G.f1 - Gp.f1, a.kxy, F.f2 - Fm.f2) * a.idx;
-    const T r3 = fma(G.f3 - Gp.f3, a.kxy, F.f3 - Fm.f3) * a.idx;
+    const T r0 = fma(G.f0 - Gp.f0, a.kxy, F.f0 - Fm.f0);
+    const T r1 = fma(G.f2 - Gp.f2, a.kxy, F.f1 - Fm.f1);
+    const T r2 = fma(G.f1 - Gp.f1, a.kxy, F.f2 - Fm.f2);
+    const T r3 = fma(G.f3 - Gp.f3, a.kxy, F.f3 - Fm.f3);
 
     // Mass fractions: reconstructed like the primitive variables and
     // carried by the face mass flux from its upwind side, (rho_A u*) y_A.
@@ -240,17 +243,17 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       const T sxs = sweby(shr1(dp), dp, beta);
       const T sxs1 = shl1(sxs);
       const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? yo.v[s] : yr1);
-      rs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy)) * a.idx;
+      rs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy));
     }
 
     const int sl = o % 3;
-    const T u0 = combine<MODE>(my[sl][0][lane], bc[0], r0, dt);
-    const T u1 = combine<MODE>(my[sl][1][lane], bc[1], r1, dt);
-    const T u2 = combine<MODE>(my[sl][2][lane], bc[2], r2, dt);
-    const T u3 = combine<MODE>(my[sl][3][lane], bc[3], r3, dt);
+    const T u0 = combine<MODE>(my[sl][0][lane], bc[0], r0, dtx, a.idx);
+    const T u1 = combine<MODE>(my[sl][1][lane], bc[1], r1, dtx, a.idx);
+    const T u2 = combine<MODE>(my[sl][2][lane], bc[2], r2, dtx, a.idx);
+    const T u3 = combine<MODE>(my[sl][3][lane], bc[3], r3, dtx, a.idx);
     T us_[NS > 0 ? NS : 1];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) us_[s] = combine<MODE>(my[sl][4 + s][lane], bc[4 + s], rs[s], dt);
+    for (int s = 0; s < NS; ++s) us_[s] = combine<MODE>(my[sl][4 + s][lane], bc[4 + s], rs[s], dtx, a.idx);
     if constexpr (MODE == kCorrector) {
       if (o + 2 < y1) load_base(off + 2 * nx, bc);
     }
@@ -487,6 +490,7 @@ static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.kxy = T(g.dx / g.dy);
+  a.rdx = 1.0 / g.dx;
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;

@@ -40,9 +40,16 @@ struct FusedArgs {
   int blocks_x, blocks, blocks_pad;
   long long plane;
   T gamma, gm1, inv_gm1, beta, idx, idy, kxy;
+  double rdx;  // 1 / dx, for dt / dx
   double dt;
   int dt_dev, reduce;
 };
+
+// FP64 with two or more mass fractions is short of registers (more than
+// 256 VGPRs would leave one wave per SIMD): it recomputes the window's row
+// difference instead of carrying it, and runs one row per loop trip.
+template <typename T, int NS>
+constexpr bool regs_to_spare() { return !(sizeof(T) == 8 && NS >= 2); }
 
 // Reconstruction variables of one row: the Euler part (primitive, or
 // conservative under CONS) and the mass fractions y_k = (rho y_k) / rho.
@@ -64,11 +71,12 @@ __device__ __forceinline__ RowV<T, NS> row_vars(const T (&q)[NF], T gm1) {
   return r;
 }
 
-// y-window of one stage: rows a and a+1, the y-slopes of row a and the
-// fluxes through face a-1/2, for the Euler variables and the fractions.
+// y-window of one stage: rows a and a+1, their difference, the y-slopes
+// of row a and the fluxes through face a-1/2, for the Euler variables and
+// the fractions.
 template <typename T, int NS>
 struct Win {
-  Prim<T> w0, w1, s0;
+  Prim<T> w0, w1, d1, s0;
   Flux<T> g;
   Frac<T, NS> y0, y1, sy0, gy;
 };
@@ -81,7 +89,8 @@ __device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const 
   Win<T, NS> W;
   const Prim<T> d_mid = sub(r0.w, rb.w);
   const Prim<T> s_b = slope(sub(rb.w, ra.w), d_mid, beta);
-  W.s0 = slope(d_mid, sub(r1.w, r0.w), beta);
+  W.d1 = sub(r1.w, r0.w);
+  W.s0 = slope(d_mid, W.d1, beta);
   bool gl;
   W.g = face_flux(face_prim<CONS>(face_plus<T, true>(rb.w, s_b), gm1),
                   face_prim<CONS>(face_minus<T, true>(r0.w, W.s0), gm1), gam, igm1, gl);
@@ -98,15 +107,21 @@ __device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const 
   return W;
 }
 
-// Residual of eq. (11) for row a of the window (every lane; valid two lanes
-// inside the valid input), given row a+2; slides the window by a row.  Same
-// arithmetic, in the same order, as the stage kernel's row, mass fractions
-// included (their face value is one fma on the operands of the upwind side,
-// so no lane shift is left to a branch).
+// Flux balance (dx times the residual of eq. (11)) of row a of the window
+// (every lane; valid two lanes inside the valid input), given row a+2;
+// slides the window by a row.  Same arithmetic, in the same order, as the
+// stage kernel's row, mass fractions included (their face value is one fma
+// on the operands of the upwind side, so no lane shift is left to a
+// branch).  The difference w1 - w0 is the one formed a row earlier (the
+// same value, when it is recomputed).
 template <bool CONS, int NS, typename T>
 __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn, T beta, T gam, T gm1, T igm1,
-                                           T kxy, T idx, T (&r)[4 + NS]) {
-  const Prim<T> s1 = slope(sub(W.w1, W.w0), sub(rn.w, W.w1), beta);
+                                           T kxy, T (&r)[4 + NS]) {
+  const Prim<T> dn = sub(rn.w, W.w1);
+  Prim<T> d1;
+  if constexpr (regs_to_spare<T, NS>()) d1 = W.d1;
+  else d1 = sub(W.w1, W.w0);
+  const Prim<T> s1 = slope(d1, dn, beta);
   bool gl, fl;
   const Flux<T> G = face_flux(face_prim<CONS>(face_plus<T, true>(W.w0, W.s0), gm1),
                               face_prim<CONS>(face_minus<T, true>(W.w1, s1), gm1), gam, igm1, gl);
@@ -118,10 +133,10 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
   const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(W.w0, sx), gm1),
                               face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1, fl);
   const Flux<T> Fm = shr1(F);
-  r[0] = fma(G.f0 - W.g.f0, kxy, F.f0 - Fm.f0) * idx;
-  r[1] = fma(G.f2 - W.g.f2, kxy, F.f1 - Fm.f1) * idx;
-  r[2] = fma(G.f1 - W.g.f1, kxy, F.f2 - Fm.f2) * idx;
-  r[3] = fma(G.f3 - W.g.f3, kxy, F.f3 - Fm.f3) * idx;
+  r[0] = fma(G.f0 - W.g.f0, kxy, F.f0 - Fm.f0);
+  r[1] = fma(G.f2 - W.g.f2, kxy, F.f1 - Fm.f1);
+  r[2] = fma(G.f1 - W.g.f1, kxy, F.f2 - Fm.f2);
+  r[3] = fma(G.f3 - W.g.f3, kxy, F.f3 - Fm.f3);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const T sy1 = sweby(W.y1.v[s] - W.y0.v[s], rn.y.v[s] - W.y1.v[s], beta);
@@ -131,12 +146,13 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
     const T sxs = sweby(shr1(dp), dp, beta);
     const T sxs1 = shl1(sxs);
     const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? W.y0.v[s] : yr1);
-    r[4 + s] = fma(gy - W.gy.v[s], kxy, fy - shr1(fy)) * idx;
+    r[4 + s] = fma(gy - W.gy.v[s], kxy, fy - shr1(fy));
     W.sy0.v[s] = sy1;
     W.gy.v[s] = gy;
   }
   W.w0 = W.w1;
   W.w1 = rn.w;
+  W.d1 = dn;
   W.s0 = s1;
   W.g = G;
   W.y0 = W.y1;
@@ -177,6 +193,7 @@ void fused_step_kernel(FusedArgs<T> a) {
   const int y1 = min(y0 + a.rows, ny);
   const long long P = a.plane;
   const double dt = a.dt_dev ? a.ctl->dt : a.dt;
+  const double dtx = dt * a.rdx;
   const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, kxy = a.kxy, idx = a.idx;
 
   const T* __restrict__ I0 = a.in;
@@ -241,12 +258,12 @@ void fused_step_kernel(FusedArgs<T> a) {
     for (int f = 0; f < NF; ++f) QA[f] = QB[f];
     if (pr + 4 <= nlast) load_row(pr + 4, QB);
     T res[NF];
-    window_row<CONS, NS>(PW, rn, beta, gam, gm1, igm1, kxy, idx, res);
+    window_row<CONS, NS>(PW, rn, beta, gam, gm1, igm1, kxy, res);
     const int sn = nslot(pr);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       S0[f] = S1[f];
-      S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), res[f], dt);
+      S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), res[f], dtx, idx);
       my_s[f][lane] = S1[f];
     }
     // U* of the strip's own rows, when asked for (halo rows belong to the
@@ -302,11 +319,11 @@ void fused_step_kernel(FusedArgs<T> a) {
     if (fresh) produce();
     const RowV<T, NS> rn = star_row();  // U* row rmap(o+2), the newest produced
     T res[NF];
-    window_row<CONS, NS>(CW, rn, beta, gam, gm1, igm1, kxy, idx, res);
+    window_row<CONS, NS>(CW, rn, beta, gam, gm1, igm1, kxy, res);
     const int sn = nslot(o);
     T u[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], res[f], dt);
+    for (int f = 0; f < NF; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], res[f], dtx, idx);
     if (out_lane) {
       const long long so = (long long)o * nx + c;
 #pragma unroll
@@ -339,10 +356,9 @@ void fused_step_kernel(FusedArgs<T> a) {
   // (about 6% of the loop's instructions).  The compiler does not unroll
   // this loop itself: it holds cross-lane operations.  FP64 with two or
   // more fractions keeps one row per trip: unrolled, it would need more
-  // than 256 VGPRs, i.e. one wave per SIMD.
-  constexpr bool kThreeRows = !(sizeof(T) == 8 && NS >= 2);
+  // than 256 VGPRs.
   int o = y0;
-  if constexpr (kThreeRows) {
+  if constexpr (regs_to_spare<T, NS>()) {
 #pragma unroll 1
     for (; o + 3 <= y1; o += 3) {
       row(o);
@@ -404,6 +420,7 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void*
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.kxy = T(g.dx / g.dy);
+  a.rdx = 1.0 / g.dx;
   a.dt = dt;
   a.dt_dev = dt_dev ? 1 : 0;
   a.reduce = reduce ? 1 : 0;
