@@ -8,7 +8,9 @@
     and adjoint steps, and between the residual JVP and VJP;
   * the misfit gradient of the adjoint workload (smooth density, uniform
     velocity and pressure) against central differences along seeded
-    directions.
+    directions;
+  * the reach of one adjoint step: a patch of radius 7 around a cell gives
+    the full-grid value at its centre, radius 6 does not.
 """
 import numpy as np
 import pytest
@@ -142,3 +144,32 @@ def test_misfit_gradient_fd(oracle_lib):
             errs.append(abs(fd - ad) / abs(ad))
         assert min(errs) <= 1e-6, errs
         assert max(errs) <= 1e-4, errs
+
+
+def test_adjoint_step_patch_locality(oracle_lib):
+    """The reach of one adjoint step, which the full-size GPU check relies
+    on: on a rough periodic 48^2 state, the adjoint step on a patch of
+    radius 10 (or 7) gathered around a cell with the periodic wrap gives
+    the full-grid value at the patch centre, to rounding, with transmissive
+    patch edges; at radius 6 the edge reaches the centre."""
+    n = 48
+    U = workloads.random_state(n, n, seed=5)
+    lam = np.random.default_rng(1).standard_normal(U.shape)
+    P = oracle.Params(n, n, 1.0 / n, 1.0 / n, 1.4, 0.5, 1.5, oracle.PERIODIC, oracle.PERIODIC)
+    rc, dt = oracle.dt(P, U)
+    full = oracle.adjoint_step(P, U, dt, lam)
+    scale = np.abs(full).max(axis=(1, 2))
+
+    def worst(r):
+        Pp = oracle.Params(2 * r + 1, 2 * r + 1, 1.0 / n, 1.0 / n, 1.4, 0.5, 1.5, oracle.TRANSMISSIVE,
+                           oracle.TRANSMISSIVE)
+        w = 0.0
+        for i, j in [(0, 0), (5, 40), (47, 47), (20, 3), (33, 17)]:
+            xs, ys = np.arange(i - r, i + r + 1) % n, np.arange(j - r, j + r + 1) % n
+            ref = oracle.adjoint_step(Pp, np.ascontiguousarray(U[:, ys][:, :, xs]), dt,
+                                      np.ascontiguousarray(lam[:, ys][:, :, xs]))[:, r, r]
+            w = max(w, float(np.max(np.abs(ref - full[:, j, i]) / scale)))
+        return w
+
+    assert worst(10) <= 1e-15 and worst(7) <= 1e-15
+    assert worst(6) > 1e-10
