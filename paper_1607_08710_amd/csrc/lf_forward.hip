@@ -221,10 +221,10 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     // as the flux balance s = dF + dG (dx/dy) with R = s / dx (the stage
     // combination takes dt / dx): with square cells dx/dy = 1 and the
     // single rounding of dF + dG keeps the x/y mirror symmetry exact.
-    const T r0 = fma(G.f0 - Gp.f0, a.kxy, F.f0 - Fm.f0);
-    const T r1 = fma(G.f2 - Gp.f2, a.kxy, F.f1 - Fm.f1);
-    const T r2 = fma(G.f1 - Gp.f1, a.kxy, F.f2 - Fm.f2);
-    const T r3 = fma(G.f3 - Gp.f3, a.kxy, F.f3 - Fm.f3);
+    const T b0 = fma(G.f0 - Gp.f0, a.kxy, F.f0 - Fm.f0);
+    const T b1 = fma(G.f2 - Gp.f2, a.kxy, F.f1 - Fm.f1);
+    const T b2 = fma(G.f1 - Gp.f1, a.kxy, F.f2 - Fm.f2);
+    const T b3 = fma(G.f3 - Gp.f3, a.kxy, F.f3 - Fm.f3);
 
     // Mass fractions: reconstructed like the primitive variables and
     // carried by the face mass flux from its upwind side, (rho_A u*) y_A.
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     // as a select of two fmas, the compiler may branch on the side and
     // move the lane shift of the right cell's slope into one arm, where
     // the lanes of the other arm are inactive and read as zero.
-    T rs[NS > 0 ? NS : 1];
+    T bs[NS > 0 ? NS : 1];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       syo1.v[s] = sweby(yo1.v[s] - yo.v[s], yn.v[s] - yo1.v[s], beta);
@@ -243,17 +243,17 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       const T sxs = sweby(shr1(dp), dp, beta);
       const T sxs1 = shl1(sxs);
       const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? yo.v[s] : yr1);
-      rs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy));
+      bs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy));
     }
 
     const int sl = o % 3;
-    const T u0 = combine<MODE>(my[sl][0][lane], bc[0], r0, dtx, a.idx);
-    const T u1 = combine<MODE>(my[sl][1][lane], bc[1], r1, dtx, a.idx);
-    const T u2 = combine<MODE>(my[sl][2][lane], bc[2], r2, dtx, a.idx);
-    const T u3 = combine<MODE>(my[sl][3][lane], bc[3], r3, dtx, a.idx);
+    const T u0 = combine<MODE>(my[sl][0][lane], bc[0], b0, dtx, a.idx);
+    const T u1 = combine<MODE>(my[sl][1][lane], bc[1], b1, dtx, a.idx);
+    const T u2 = combine<MODE>(my[sl][2][lane], bc[2], b2, dtx, a.idx);
+    const T u3 = combine<MODE>(my[sl][3][lane], bc[3], b3, dtx, a.idx);
     T us_[NS > 0 ? NS : 1];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) us_[s] = combine<MODE>(my[sl][4 + s][lane], bc[4 + s], rs[s], dtx, a.idx);
+    for (int s = 0; s < NS; ++s) us_[s] = combine<MODE>(my[sl][4 + s][lane], bc[4 + s], bs[s], dtx, a.idx);
     if constexpr (MODE == kCorrector) {
       if (o + 2 < y1) load_base(off + 2 * nx, bc);
     }

@@ -257,13 +257,13 @@ void fused_step_kernel(FusedArgs<T> a) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) QA[f] = QB[f];
     if (pr + 4 <= nlast) load_row(pr + 4, QB);
-    T res[NF];
-    window_row<CONS, NS>(PW, rn, beta, gam, gm1, igm1, kxy, res);
+    T bal[NF];  // flux balances
+    window_row<CONS, NS>(PW, rn, beta, gam, gm1, igm1, kxy, bal);
     const int sn = nslot(pr);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       S0[f] = S1[f];
-      S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), res[f], dtx, idx);
+      S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), bal[f], dtx, idx);
       my_s[f][lane] = S1[f];
     }
     // U* of the strip's own rows, when asked for (halo rows belong to the
@@ -318,12 +318,12 @@ void fused_step_kernel(FusedArgs<T> a) {
     const bool fresh = o + 2 <= phi;
     if (fresh) produce();
     const RowV<T, NS> rn = star_row();  // U* row rmap(o+2), the newest produced
-    T res[NF];
-    window_row<CONS, NS>(CW, rn, beta, gam, gm1, igm1, kxy, res);
+    T bal[NF];
+    window_row<CONS, NS>(CW, rn, beta, gam, gm1, igm1, kxy, bal);
     const int sn = nslot(o);
     T u[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], res[f], dtx, idx);
+    for (int f = 0; f < NF; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], bal[f], dtx, idx);
     if (out_lane) {
       const long long so = (long long)o * nx + c;
 #pragma unroll
