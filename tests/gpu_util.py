@@ -99,6 +99,6 @@ def oracle_step_at(U, cfg, dt, cells, r=4):
         patch, ic, jc = sample_patch(U, cfg, i, j, r)
         P = oracle.Params(patch.shape[2], patch.shape[1], cfg["dx"], cfg["dy"], cfg["gamma"],
                           cfg["cfl"], cfg["beta"], oracle.TRANSMISSIVE, oracle.TRANSMISSIVE,
-                          ns=U.shape[0] - 4)
+                          ns=U.shape[0] - 4, recon=cfg.get("recon", 0))
         out[k] = oracle.step(P, patch, dt)[:, jc, ic]
     return out
