@@ -314,16 +314,22 @@ def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
     torch.cuda.synchronize()
     bare_us = e0.elapsed_time(e1) / 1e3 / reps
     del us
-    # full gradient of J = 1/2 dx dy sum (rho_N - rho_0)^2 w.r.t. U0
+    # full gradient of J = 1/2 dx dy sum (rho_N - rho_0)^2 w.r.t. U0; one
+    # untimed rollout first, so that the timed one finds the allocator's
+    # pool (10 checkpoints, a segment of 20 states and 20 U*: ~27 GB in
+    # FP64 at 4096^2) already grown
     rho_t = U0[0].clone()
-    x = U0.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    e0.record()
-    UN = rollout(x, S, [dt] * steps, ckpt_every=ckpt)
-    J = 0.5 * cfg["dx"] * cfg["dy"] * ((UN[0] - rho_t) ** 2).sum()
-    J.backward()
-    e1.record()
-    torch.cuda.synchronize()
+    for timed in (False, True):
+        x = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        e0.record()
+        UN = rollout(x, S, [dt] * steps, ckpt_every=ckpt)
+        J = 0.5 * cfg["dx"] * cfg["dy"] * ((UN[0] - rho_t) ** 2).sum()
+        J.backward()
+        e1.record()
+        torch.cuda.synchronize()
+        if not timed:
+            del x, UN, J
     full = e0.elapsed_time(e1) / 1e3
     esz = 8 if dtype_flag == L.LF_F64 else 4
     res = {
