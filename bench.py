@@ -13,9 +13,10 @@ roofline of the dominant kernel (the single-pass step, bound by VALU issue)
 and of the two-stage design's corrector against HBM, each from HIP events
 on the stream the kernel runs on; the FP32 path, the two-stage path, the
 mass-fraction runs, the four-quadrant problem at 8192^2, the isentropic
-vortex at 4096^2 (rate and error against the exact solution) and the
-adjoint (lf_adjoint_step and the checkpointed full gradient at 4096^2) as
-extra objects; a plain device copy's bandwidth beside the rooflines; and
+vortex at 4096^2 (rate and error against the exact solution), one strip
+of the 16384^2 grid split into 8 (lf_step_halo with its ghost rows: one
+GPU's share) and the adjoint (lf_adjoint_step and the checkpointed full
+gradient at 4096^2) as extra objects; a plain device copy's bandwidth beside the rooflines; and
 the FP64 CPU oracle timed on a bounded sample on this host (all threads,
 and one thread).
 
@@ -261,6 +262,67 @@ def vortex_leg(L, W, n, t_end=2.0):
     return res
 
 
+def shard_leg(L, W, n, shards, steps, warmup):
+    """One GPU's share of the n^2 Kelvin-Helmholtz grid split into `shards`
+    strips of rows: lf_step_halo on the first strip (n x n/shards cells),
+    each step preceded by the refresh of its ghost rows, 4 below and 4
+    above, copied on the device from the neighbouring strips' rows (in
+    place of the exchange between GPUs).  Reports the strip's step time,
+    the ghost-row copy time and cell-updates/s of the strip; and checks
+    that the strips stepped this way give the whole grid's lf_step bit for
+    bit."""
+    import torch
+    U, cfg = W.kelvin_helmholtz_torch(n)
+    h = n // shards
+    S_all = make_solver(L, cfg, L.LF_F64)
+    dt = S_all.dt(U)
+    S = make_solver(L, dict(cfg, ny=h), L.LF_F64)
+    G = L.GHOST_ROWS
+    glo = torch.empty((4, G, n), dtype=U.dtype, device=U.device)
+    ghi = torch.empty_like(glo)
+    a = U[:, :h].contiguous()
+    b = torch.empty_like(a)
+
+    def refresh():
+        glo.copy_(U[:, n - G:])      # the strip below, across the periodic wrap
+        ghi.copy_(U[:, h:h + G])     # the strip above
+
+    for _ in range(warmup):
+        refresh()
+        S.step_halo(a, glo, ghi, b, dt)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(steps):
+        refresh()
+    ev[1].record()
+    for _ in range(steps):
+        S.step_halo(a, glo, ghi, b, dt)
+        a, b = b, a
+    ev[2].record()
+    torch.cuda.synchronize()
+    copy_ms = ev[0].elapsed_time(ev[1]) / steps
+    step_ms = ev[1].elapsed_time(ev[2]) / steps
+    # every strip from the same U^n against the whole grid's step
+    ref = torch.empty_like(U)
+    S_all.step(U, ref, dt)
+    same = True
+    for k in range(shards):
+        y0 = k * h
+        rows = torch.arange(y0, y0 + h, device=U.device)
+        lo = torch.arange(y0 - G, y0, device=U.device) % n
+        hi = torch.arange(y0 + h, y0 + h + G, device=U.device) % n
+        S.step_halo(U.index_select(1, rows).contiguous(), U.index_select(1, lo).contiguous(),
+                    U.index_select(1, hi).contiguous(), b, dt)
+        same = same and torch.equal(b, ref[:, y0:y0 + h])
+    del U, ref, a, b, glo, ghi, S, S_all
+    torch.cuda.empty_cache()
+    return {"n": n, "shards": shards, "strip": [h, n], "steps": steps,
+            "step_ms": step_ms, "value": n * h / (step_ms / 1e3),
+            "ghost_copy_ms": copy_ms, "ghost_bytes_per_step": 2 * 4 * G * n * 8,
+            "strips_equal_whole_grid_step": bool(same)}
+
+
 def copy_bandwidth(nbytes=4 << 30, reps=10):
     """HBM bandwidth of a plain device-to-device copy (torch's copy kernel),
     bytes read + written per second: what a streaming kernel reaches on
@@ -438,9 +500,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="forward,species,quadrant,vortex,adjoint,cpu",
-                    help="comma list of legs to run: forward, species, quadrant, vortex, adjoint, cpu "
+    ap.add_argument("--legs", default="forward,species,quadrant,vortex,shard,adjoint,cpu",
+                    help="comma list of legs to run: forward, species, quadrant, vortex, shard, adjoint, cpu "
                          "(profiling runs use one leg so that each kernel runs at one grid size)")
+    ap.add_argument("--shards", type=int, default=8)
     ap.add_argument("--vortex-n", type=int, default=4096)
     ap.add_argument("--cpu-n", type=int, default=2048, help=argparse.SUPPRESS)
     ap.add_argument("--oracle-only", action="store_true", help=argparse.SUPPRESS)
@@ -478,7 +541,7 @@ def main():
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
     f64 = f32 = adj64 = adj32 = roofline = cpu = None
-    species = roofline_two_stage = recon64 = quadrant = vortex = None
+    species = roofline_two_stage = recon64 = quadrant = vortex = shard = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
         f64 = forward_leg(L, W, args.n, L.LF_F64, args.steps, args.warmup, args.kernel_reps)
@@ -542,6 +605,12 @@ def main():
         log(f"  FP64 {vortex['f64']['value'] / 1e9:.2f} G cell-updates/s over {vortex['f64']['steps']} steps, "
             f"rho L1 error {vortex['f64']['rho_l1_error']:.3e}; FP32 {vortex['f32']['value'] / 1e9:.2f} G, "
             f"{vortex['f32']['rho_l1_error']:.3e}")
+    if "shard" in legs:
+        log(f"one strip of {args.n}^2 in {args.shards}: lf_step_halo on {args.n // args.shards} x {args.n} cells")
+        shard = shard_leg(L, W, args.n, args.shards, args.steps // 2, args.warmup)
+        log(f"  {shard['step_ms']:.3f} ms/step ({shard['value'] / 1e9:.2f} G cell-updates/s), ghost rows "
+            f"{shard['ghost_copy_ms'] * 1e3:.1f} us/step; strips equal the whole-grid step: "
+            f"{shard['strips_equal_whole_grid_step']}")
     if "adjoint" in legs:
         log(f"adjoint {args.adj_n}^2, {args.adj_steps} steps, checkpoints every {args.adj_ckpt}")
         adj64 = adjoint_leg(L, W, args.adj_n, L.LF_F64, args.adj_steps, args.adj_ckpt, 10)
@@ -581,6 +650,7 @@ def main():
         "conservative_reconstruction": recon64,
         "four_quadrant": quadrant,
         "vortex": vortex,
+        "shard": shard,
         "adjoint": {"n": args.adj_n, "steps": args.adj_steps, "ckpt_every": args.adj_ckpt,
                     "f64": adj64, "f32": adj32},
         "paper_context": {"value": 81.0e6, "unit": "cell-updates/s",

@@ -63,6 +63,9 @@ typedef enum {
 typedef enum { LF_F64 = 0, LF_F32 = 1 } lf_dtype;
 
 #define LF_MAX_SPECIES 4
+/* Rows a strip of a larger grid needs beyond each of its ends for one
+ * step (lf_step_halo): two for each of the step's two stages. */
+#define LF_GHOST_ROWS 4
 
 typedef enum { LF_RECON_PRIMITIVE = 0, LF_RECON_CONSERVATIVE = 1 } lf_recon;
 typedef enum { LF_BC_PERIODIC = 0, LF_BC_TRANSMISSIVE = 1 } lf_bc;
@@ -115,10 +118,10 @@ int lf_dt(lf_ctx *ctx, const void *U, void *ws, void *stream, double *dt_out);
  * flux balance of eq. (11).  Unp1 may equal Un (in-place update); any other
  * overlap is LF_ERR_ARG.  dt must be finite and >= 0.  In the FP32 context
  * the states are float, the flux arithmetic is float and every stage
- * update is formed in FP64 and rounded once.  With Unp1 != Un and no mass
- * fractions the step is one single-pass kernel (U* never leaves the chip);
- * otherwise U* goes through the workspace.  Either way the result is
- * bitwise that of lf_stage(1) followed by lf_stage(2). */
+ * update is formed in FP64 and rounded once.  With Unp1 != Un the step is
+ * one single-pass kernel (U* never leaves the chip); in place, U* goes
+ * through the workspace.  Either way the result is bitwise that of
+ * lf_stage(1) followed by lf_stage(2). */
 int lf_step(lf_ctx *ctx, const void *Un, void *Unp1, double dt, void *ws, void *stream);
 
 /* lf_step into a separate buffer that also writes the predictor state
@@ -129,6 +132,22 @@ int lf_step(lf_ctx *ctx, const void *Un, void *Unp1, double dt, void *ws, void *
  * must not overlap each other (LF_ERR_ARG). */
 int lf_step_save(lf_ctx *ctx, const void *Un, void *Unp1, void *Ustar, double dt, void *ws,
                  void *stream);
+
+/* One lf_step of a horizontal strip of a larger grid, async: the unit of
+ * work of one GPU when the grid is split into strips of rows (Sec. 5,
+ * items 2-11 on the strip).  The context describes the strip (ny = its
+ * rows; bc_x applies, bc_y is not used).  The LF_GHOST_ROWS rows below
+ * row 0 and above row ny-1 are read from ghost_lo and ghost_hi, each
+ * [4 + n_species][LF_GHOST_ROWS][nx] in the context's dtype (ghost_lo row
+ * k is strip row k - LF_GHOST_ROWS, ghost_hi row k is strip row ny + k),
+ * which the caller fills from the neighbouring strips' U^n before the
+ * call (across GPUs, by the halo exchange).  Every strip of a grid
+ * stepped with its neighbours' rows (taken across the wrap for a periodic
+ * y) gives, together, lf_step of the whole grid bit for bit.  Single
+ * pass.  The inputs (Un and the ghost rows) may overlap each other; Unp1
+ * and ws must not overlap any input or each other (LF_ERR_ARG). */
+int lf_step_halo(lf_ctx *ctx, const void *Un, const void *ghost_lo, const void *ghost_hi,
+                 void *Unp1, double dt, void *ws, void *stream);
 
 /* One stage of the Heun step at the caller's dt, async (the two kernels
  * lf_step chains, exposed for callers that schedule stages themselves):

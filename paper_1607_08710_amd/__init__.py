@@ -29,9 +29,10 @@ LF_MAX_SPECIES = 4
 LF_RECON_PRIMITIVE, LF_RECON_CONSERVATIVE = 0, 1
 
 # Names exported by the C ABI (include/lagrangeflux.h).
-ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_step_save", "lf_stage",
-                 "lf_advance", "lf_residual", "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar",
-                 "lf_totals")
+ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_step_save", "lf_step_halo",
+                 "lf_stage", "lf_advance", "lf_residual", "lf_residual_vjp", "lf_adjoint_step",
+                 "lf_adjoint_step_ustar", "lf_totals")
+GHOST_ROWS = 4  # LF_GHOST_ROWS: rows a strip needs beyond each end for one step
 
 
 class LFError(RuntimeError):
@@ -78,6 +79,7 @@ def lib() -> ctypes.CDLL:
         L.lf_dt.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
         L.lf_step.argtypes = [vp, vp, vp, d, vp, vp]
         L.lf_step_save.argtypes = [vp, vp, vp, vp, d, vp, vp]
+        L.lf_step_halo.argtypes = [vp, vp, vp, vp, vp, d, vp, vp]
         L.lf_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, d, ctypes.c_int, vp, vp]
         L.lf_advance.argtypes = [vp, vp, d, d, i64, vp, vp, ctypes.POINTER(d), ctypes.POINTER(i64),
                                  ctypes.POINTER(d), i64]
@@ -86,8 +88,8 @@ def lib() -> ctypes.CDLL:
         L.lf_adjoint_step.argtypes = [vp, vp, d, vp, vp, vp, vp]
         L.lf_adjoint_step_ustar.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
         L.lf_totals.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
-        for name in ("lf_init", "lf_dt", "lf_step", "lf_step_save", "lf_stage", "lf_advance", "lf_residual",
-                     "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar", "lf_totals"):
+        for name in ("lf_init", "lf_dt", "lf_step", "lf_step_save", "lf_step_halo", "lf_stage", "lf_advance",
+                     "lf_residual", "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar", "lf_totals"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -188,6 +190,21 @@ class Solver:
         """One step into Unp1 that also writes the step's predictor state U*."""
         _check(lib().lf_step_save(self._ctx, self._arg(Un, "Un"), self._arg(Unp1, "Unp1"), self._arg(Ustar, "Ustar"),
                                   float(dt), ctypes.c_void_p(self.ws.data_ptr()), self._stream()), "lf_step_save")
+
+    def step_halo(self, Un, ghost_lo, ghost_hi, Unp1, dt: float):
+        """One step of this solver's grid as a strip of a larger one: the
+        GHOST_ROWS rows below and above it are given, each a contiguous
+        (fields, GHOST_ROWS, nx) tensor (ghost_lo row k is strip row
+        k - GHOST_ROWS, ghost_hi row k is strip row ny + k)."""
+        gshape = (self.shape[0], GHOST_ROWS, self.shape[2])
+        for t, name in ((ghost_lo, "ghost_lo"), (ghost_hi, "ghost_hi")):
+            if t.device != self.device or t.dtype != self.torch_dtype or tuple(t.shape) != gshape \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name}: expected a contiguous {self.torch_dtype} tensor of shape {gshape} on "
+                                 f"{self.device}, got {t.dtype} {tuple(t.shape)} on {t.device}")
+        _check(lib().lf_step_halo(self._ctx, self._arg(Un, "Un"), ctypes.c_void_p(ghost_lo.data_ptr()),
+                                  ctypes.c_void_p(ghost_hi.data_ptr()), self._arg(Unp1, "Unp1"), float(dt),
+                                  ctypes.c_void_p(self.ws.data_ptr()), self._stream()), "lf_step_halo")
 
     def stage(self, stage: int, inp, out, dt: float, base=None, reduce: bool = False):
         """One Heun stage: 1 = predictor (out = in - dt R(in)), 2 = corrector

@@ -14,6 +14,7 @@
 #include "lf_internal.h"
 
 static_assert(LF_MAX_SPECIES == lf::kMaxSpecies, "species cap of the ABI and the kernels");
+static_assert(LF_GHOST_ROWS == lf::kGhostRows, "ghost rows of a strip");
 
 struct lf_ctx {
   lf::Grid g;
@@ -140,6 +141,23 @@ int lf_step_save(lf_ctx* ctx, const void* Un, void* Unp1, void* Ustar, double dt
   if (overlap(Un, n, ws, w) || overlap(Unp1, n, ws, w) || overlap(Ustar, n, ws, w)) return LF_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return hip_status(lf::launch_fused_step(ctx->g, Un, Unp1, Ustar, dt, nullptr, false, false, s));
+}
+
+int lf_step_halo(lf_ctx* ctx, const void* Un, const void* ghost_lo, const void* ghost_hi, void* Unp1, double dt,
+                 void* ws, void* stream) {
+  if (!ctx || !Un || !ghost_lo || !ghost_hi || !Unp1 || !ws) return LF_ERR_ARG;
+  if (!(dt >= 0.0) || !isfinite(dt)) return LF_ERR_ARG;
+  const size_t n = ctx->state_bytes, w = ctx->L.total;
+  const size_t gb = ctx->state_bytes / (size_t)ctx->g.ny * LF_GHOST_ROWS;  // [fields][4][nx]
+  if (overlap(Unp1, n, Un, n) || overlap(Unp1, n, ghost_lo, gb) || overlap(Unp1, n, ghost_hi, gb) ||
+      overlap(Unp1, n, ws, w))
+    return LF_ERR_ARG;
+  if (overlap(Un, n, ws, w) || overlap(ghost_lo, gb, ws, w) || overlap(ghost_hi, gb, ws, w)) return LF_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lf::GhostRows gh;
+  gh.lo = ghost_lo;
+  gh.hi = ghost_hi;
+  return hip_status(lf::launch_fused_step(ctx->g, Un, Unp1, nullptr, dt, nullptr, false, false, s, gh));
 }
 
 int lf_stage(lf_ctx* ctx, int stage, const void* in, const void* base, void* out, double dt, int reduce,

@@ -26,7 +26,11 @@ constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kDtHist = 4096;    // per-step dt records kept on the device
 constexpr int kMaxSpecies = 4;   // passive mass fractions a state may carry
 
-enum : int { kBcPeriodic = 0, kBcTransmissive = 1 };
+// y-boundaries; kBcGhost (single-pass step of a strip of a larger grid
+// only): the kGhostRows rows beyond each end of the strip are read from
+// caller-supplied ghost rows.
+enum : int { kBcPeriodic = 0, kBcTransmissive = 1, kBcGhost = 2 };
+constexpr int kGhostRows = 4;
 
 // Stage kernel modes.
 enum StageMode : int { kResidual = 0, kPredictor = 1, kCorrector = 2 };
@@ -55,6 +59,7 @@ struct Ctl {
 
 template <int BC>
 __device__ __forceinline__ int map_index(int k, int n) {
+  static_assert(BC == kBcPeriodic || BC == kBcTransmissive, "ghost rows are not an index mapping");
   if constexpr (BC == kBcPeriodic) {
     k %= n;
     return k < 0 ? k + n : k;

@@ -35,6 +35,8 @@ struct FusedArgs {
   const T* in;  // U^n
   T* out;       // U^{n+1}, must not overlap in
   T* ustar;     // nullable: receives the predictor state U* of every cell
+  const T* ghost_lo;  // BCY == kBcGhost: rows -4 .. -1, [NF][4][nx]
+  const T* ghost_hi;  // BCY == kBcGhost: rows ny .. ny+3, [NF][4][nx]
   Ctl* ctl;
   int nx, ny, rows;
   int blocks_x, blocks, blocks_pad;
@@ -198,9 +200,29 @@ void fused_step_kernel(FusedArgs<T> a) {
 
   const T* __restrict__ I0 = a.in;
   auto load_row = [&](int row, T (&q)[NF]) {
-    const int off = map_index<BCY>(row, ny) * nx + cm;
+    if constexpr (BCY == kBcGhost) {
+      // the strip's rows, or the ghost rows beyond its ends (every row
+      // read lies in -kGhostRows .. ny+kGhostRows-1: see nlast below)
+      const T* src = I0;
+      long long pl = P;
+      int r = row;
+      if (row < 0) {
+        src = a.ghost_lo;
+        pl = (long long)kGhostRows * nx;
+        r = row + kGhostRows;
+      } else if (row >= ny) {
+        src = a.ghost_hi;
+        pl = (long long)kGhostRows * nx;
+        r = row - ny;
+      }
+      const int off = r * nx + cm;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) q[f] = I0[f * P + off];
+      for (int f = 0; f < NF; ++f) q[f] = src[f * pl + off];
+    } else {
+      const int off = map_index<BCY>(row, ny) * nx + cm;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) q[f] = I0[f * P + off];
+    }
   };
 
   // U^n ring (rows o .. o+4 are alive while row o is finished) and the
@@ -220,7 +242,8 @@ void fused_step_kernel(FusedArgs<T> a) {
   auto rmap = [&](int r) { return YT ? min(max(r, 0), ny - 1) : r; };
 
   // Rows of U* the corrector needs: y0-2 .. y1+1; the predictor produces
-  // the ones that are not transmissive ghosts.
+  // the ones that are not transmissive ghosts, reading U^n rows plo-2 ..
+  // nlast (y0-4 .. y1+3 unless transmissive: within the ghost rows).
   const int plo = YT ? max(y0 - 2, 0) : y0 - 2;
   const int phi = YT ? min(y1 + 1, ny - 1) : y1 + 1;
   const int nlast = phi + 2;  // last U^n row the predictor reads
@@ -399,12 +422,14 @@ static int fused_rows(int nx, int ny, int esize) {
 
 template <typename T, int BCX, int BCY, int NS, bool CONS>
 static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
-                                 bool dt_dev, bool reduce, hipStream_t s) {
+                                 bool dt_dev, bool reduce, const GhostRows& gh, hipStream_t s) {
   constexpr int WPB = waves_per_block<T>();
   FusedArgs<T> a;
   a.in = static_cast<const T*>(in);
   a.out = static_cast<T*>(out);
   a.ustar = static_cast<T*>(ustar);
+  a.ghost_lo = static_cast<const T*>(gh.lo);
+  a.ghost_hi = static_cast<const T*>(gh.hi);
   a.ctl = ctl;
   a.nx = g.nx;
   a.ny = g.ny;
@@ -432,35 +457,39 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void*
 
 template <typename T, int BCX, int BCY>
 static hipError_t launch_fused_ns(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
-                                  bool dt_dev, bool reduce, hipStream_t s) {
+                                  bool dt_dev, bool reduce, const GhostRows& gh, hipStream_t s) {
   static_assert(kMaxSpecies == 4, "one instantiation per species count");
-  if (g.recon) return launch_fused_t<T, BCX, BCY, 0, true>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+  if (g.recon) return launch_fused_t<T, BCX, BCY, 0, true>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
   switch (g.ns) {
-    case 0: return launch_fused_t<T, BCX, BCY, 0, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-    case 1: return launch_fused_t<T, BCX, BCY, 1, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-    case 2: return launch_fused_t<T, BCX, BCY, 2, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-    case 3: return launch_fused_t<T, BCX, BCY, 3, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-    default: return launch_fused_t<T, BCX, BCY, 4, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+    case 0: return launch_fused_t<T, BCX, BCY, 0, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+    case 1: return launch_fused_t<T, BCX, BCY, 1, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+    case 2: return launch_fused_t<T, BCX, BCY, 2, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+    case 3: return launch_fused_t<T, BCX, BCY, 3, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+    default: return launch_fused_t<T, BCX, BCY, 4, false>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
   }
+}
+
+template <typename T, int BCX>
+static hipError_t launch_fused_by(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
+                                  bool dt_dev, bool reduce, const GhostRows& gh, hipStream_t s) {
+  if (gh.lo) return launch_fused_ns<T, BCX, kBcGhost>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+  if (g.bc_y == kBcPeriodic)
+    return launch_fused_ns<T, BCX, kBcPeriodic>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+  return launch_fused_ns<T, BCX, kBcTransmissive>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
 }
 
 template <typename T>
 static hipError_t launch_fused_bc(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
-                                  bool dt_dev, bool reduce, hipStream_t s) {
-  if (g.bc_x == kBcPeriodic) {
-    if (g.bc_y == kBcPeriodic)
-      return launch_fused_ns<T, kBcPeriodic, kBcPeriodic>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-    return launch_fused_ns<T, kBcPeriodic, kBcTransmissive>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-  }
-  if (g.bc_y == kBcPeriodic)
-    return launch_fused_ns<T, kBcTransmissive, kBcPeriodic>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_ns<T, kBcTransmissive, kBcTransmissive>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+                                  bool dt_dev, bool reduce, const GhostRows& gh, hipStream_t s) {
+  if (g.bc_x == kBcPeriodic)
+    return launch_fused_by<T, kBcPeriodic>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+  return launch_fused_by<T, kBcTransmissive>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
 }
 
 hipError_t launch_fused_step(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
-                             bool dt_dev, bool reduce, hipStream_t s) {
-  if (g.dtype == 0) return launch_fused_bc<double>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
-  return launch_fused_bc<float>(g, in, out, ustar, dt, ctl, dt_dev, reduce, s);
+                             bool dt_dev, bool reduce, hipStream_t s, GhostRows gh) {
+  if (g.dtype == 0) return launch_fused_bc<double>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
+  return launch_fused_bc<float>(g, in, out, ustar, dt, ctl, dt_dev, reduce, gh, s);
 }
 
 }  // namespace lf

@@ -45,10 +45,18 @@ Layout make_layout(const Grid& g);
 // reduce: corrector only, reduce the wave speed of the output into ctl.
 hipError_t launch_stage(const Grid& g, int mode, const void* in, const void* base, void* out,
                         double dt, Ctl* ctl, bool dt_dev, bool reduce, hipStream_t s);
+// Ghost rows of a strip of a larger grid: kGhostRows rows below row 0
+// (lo) and above row ny-1 (hi), [fields][kGhostRows][nx] each.
+struct GhostRows {
+  const void* lo = nullptr;
+  const void* hi = nullptr;
+};
 // One whole Heun step in a single pass, out = step(in); in and out must
-// not overlap.  ustar (nullable) receives the predictor state U*.
+// not overlap.  ustar (nullable) receives the predictor state U*.  With
+// ghost rows, rows beyond the grid's ends are read from them instead of
+// following bc_y.
 hipError_t launch_fused_step(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
-                             bool dt_dev, bool reduce, hipStream_t s);
+                             bool dt_dev, bool reduce, hipStream_t s, GhostRows gh = GhostRows());
 hipError_t launch_wavespeed(const Grid& g, const void* U, Ctl* ctl, hipStream_t s);
 hipError_t launch_ctl_init(Ctl* ctl, double t0, double t_end, long long max_steps, double cfl,
                            hipStream_t s);

@@ -120,6 +120,12 @@ def test_entry_points_validate_before_hip():
     assert lib.lf_step_save(ctx, A, A, C, 0.1, W, None) == E          # no in-place form
     assert lib.lf_adjoint_step_ustar(ctx, A, B, 0.1, C, B, W, None) == E  # lam_n overlaps U*
     assert lib.lf_adjoint_step_ustar(ctx, A, None, 0.1, C, B, W, None) == E
+    ghost = 4 * 4 * 64 * 8  # [4 fields][4 rows][64] doubles
+    assert lib.lf_step_halo(ctx, A, None, C, B, 0.1, W, None) == E
+    assert lib.lf_step_halo(ctx, A, C, C, B, float("nan"), W, None) == E
+    assert lib.lf_step_halo(ctx, A, C, C, A, 0.1, W, None) == E                      # output is the input
+    assert lib.lf_step_halo(ctx, A, C, vp(B.value + ghost // 2), B, 0.1, W, None) == E  # output overlaps ghost_hi
+    assert lib.lf_step_halo(ctx, A, vp(W.value + 64), C, B, 0.1, W, None) == E     # ghost_lo inside ws
     lib.lf_destroy(ctx)
 
 
