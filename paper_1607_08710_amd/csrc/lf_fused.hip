@@ -29,6 +29,10 @@ namespace lf {
 
 constexpr int kFHalo = 4;
 constexpr int kFTileW = kWave - 2 * kFHalo;  // 56 output columns per wave
+// Waves per block, both precisions (the waves are independent; a block
+// only numbers adjacent tiles).  Measured at 16384^2: FP32 runs 2.5%
+// faster than with 8, FP64 0.7% faster than with 2.
+constexpr int kFusedWaves = 4;
 
 template <typename T>
 struct FusedArgs {
@@ -168,11 +172,11 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
 // registers, and one LDS row of U* serves the reads across lanes.  Results
 // are stored straight from the lanes (no staging, no block barrier).
 template <typename T, int BCX, int BCY, int NS, bool CONS>
-__global__ __launch_bounds__(kWave * waves_per_block<T>())
+__global__ __launch_bounds__(kWave * kFusedWaves)
 void fused_step_kernel(FusedArgs<T> a) {
   static_assert(!CONS || NS == 0, "the conservative reconstruction is built without mass fractions");
   constexpr int NF = 4 + NS;  // conservative fields: Euler, then rho*y_k
-  constexpr int WPB = waves_per_block<T>();
+  constexpr int WPB = kFusedWaves;
   constexpr bool XT = BCX == kBcTransmissive;
   constexpr bool YT = BCY == kBcTransmissive;
   if (a.dt_dev && a.ctl->done) return;
@@ -423,7 +427,7 @@ static int fused_rows(int nx, int ny, int esize) {
 template <typename T, int BCX, int BCY, int NS, bool CONS>
 static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void* ustar, double dt, Ctl* ctl,
                                  bool dt_dev, bool reduce, const GhostRows& gh, hipStream_t s) {
-  constexpr int WPB = waves_per_block<T>();
+  constexpr int WPB = kFusedWaves;
   FusedArgs<T> a;
   a.in = static_cast<const T*>(in);
   a.out = static_cast<T*>(out);
