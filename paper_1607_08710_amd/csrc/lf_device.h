@@ -343,10 +343,17 @@ __device__ __forceinline__ Prim<T> sub(const Prim<T>& a, const Prim<T>& b) {
   return {a.r - b.r, a.u - b.u, a.v - b.v, a.p - b.p};
 }
 
+// Limited slope from the backward and forward differences.  Eq. (sweby)
+// is symmetric in its two arguments (for ab > 0 they share their sign;
+// otherwise it is 0), and the forward difference goes first: it is always
+// formed just before (a lane shift or a value carried from the previous
+// row can hold anything as far as the compiler knows), so |dp| needs no
+// IEEE quieting before the min and max.  Only the sign of a zero slope
+// can differ from the other order.
 template <typename T>
 __device__ __forceinline__ Prim<T> slope(const Prim<T>& dm, const Prim<T>& dp, T beta) {
-  return {sweby(dm.r, dp.r, beta), sweby(dm.u, dp.u, beta), sweby(dm.v, dp.v, beta),
-          sweby(dm.p, dp.p, beta)};
+  return {sweby(dp.r, dm.r, beta), sweby(dp.u, dm.u, beta), sweby(dp.v, dm.v, beta),
+          sweby(dp.p, dm.p, beta)};
 }
 
 // w + s/2 in the x-face frame (u normal) or the y-face frame (v normal).

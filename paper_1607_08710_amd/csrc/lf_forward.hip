@@ -175,8 +175,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       Y1 = fractions(q1);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const T sb = sweby(yb.v[s] - ya.v[s], Y0.v[s] - yb.v[s], beta);
-        Sy0.v[s] = sweby(Y0.v[s] - yb.v[s], Y1.v[s] - Y0.v[s], beta);
+        const T sb = sweby(Y0.v[s] - yb.v[s], yb.v[s] - ya.v[s], beta);
+        Sy0.v[s] = sweby(Y1.v[s] - Y0.v[s], Y0.v[s] - yb.v[s], beta);
         Gy0.v[s] = Gf0.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? sb : Sy0.v[s], gl ? yb.v[s] : Y0.v[s]);
       }
     }
@@ -236,11 +236,11 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     T bs[NS > 0 ? NS : 1];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      syo1.v[s] = sweby(yo1.v[s] - yo.v[s], yn.v[s] - yo1.v[s], beta);
+      syo1.v[s] = sweby(yn.v[s] - yo1.v[s], yo1.v[s] - yo.v[s], beta);
       gy.v[s] = G.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? syo.v[s] : syo1.v[s], gl ? yo.v[s] : yo1.v[s]);
       const T yr1 = shl1(yo.v[s]);
       const T dp = yr1 - yo.v[s];
-      const T sxs = sweby(shr1(dp), dp, beta);
+      const T sxs = sweby(dp, shr1(dp), beta);
       const T sxs1 = shl1(sxs);
       const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? yo.v[s] : yr1);
       bs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy));

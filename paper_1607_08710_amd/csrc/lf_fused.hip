@@ -104,8 +104,8 @@ __device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const 
   W.w1 = r1.w;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const T sb = sweby(rb.y.v[s] - ra.y.v[s], r0.y.v[s] - rb.y.v[s], beta);
-    W.sy0.v[s] = sweby(r0.y.v[s] - rb.y.v[s], r1.y.v[s] - r0.y.v[s], beta);
+    const T sb = sweby(r0.y.v[s] - rb.y.v[s], rb.y.v[s] - ra.y.v[s], beta);
+    W.sy0.v[s] = sweby(r1.y.v[s] - r0.y.v[s], r0.y.v[s] - rb.y.v[s], beta);
     W.gy.v[s] = W.g.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? sb : W.sy0.v[s], gl ? rb.y.v[s] : r0.y.v[s]);
   }
   W.y0 = r0.y;
@@ -145,11 +145,11 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
   r[3] = fma(G.f3 - W.g.f3, kxy, F.f3 - Fm.f3);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const T sy1 = sweby(W.y1.v[s] - W.y0.v[s], rn.y.v[s] - W.y1.v[s], beta);
+    const T sy1 = sweby(rn.y.v[s] - W.y1.v[s], W.y1.v[s] - W.y0.v[s], beta);
     const T gy = G.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? W.sy0.v[s] : sy1, gl ? W.y0.v[s] : W.y1.v[s]);
     const T yr1 = shl1(W.y0.v[s]);
     const T dp = yr1 - W.y0.v[s];
-    const T sxs = sweby(shr1(dp), dp, beta);
+    const T sxs = sweby(dp, shr1(dp), beta);
     const T sxs1 = shl1(sxs);
     const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? W.y0.v[s] : yr1);
     r[4 + s] = fma(gy - W.gy.v[s], kxy, fy - shr1(fy));
