@@ -521,8 +521,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the Lagrange-flux path is built and measured on a single "
-              "MI355X (the multi-GPU domain decomposition is designed but not implemented); "
-              "run with --gpus 1", file=sys.stderr)
+              "MI355X (one GPU's strip of a split grid, lf_step_halo, is timed by the shard leg; the "
+              "exchange between GPUs is not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
