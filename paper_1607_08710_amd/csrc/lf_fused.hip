@@ -408,10 +408,11 @@ void fused_step_kernel(FusedArgs<T> a) {
 
 // Strip height of the fused kernel: 128 rows in FP64, 64 in FP32 (each
 // strip recomputes 4 rows of U* for its halo; measured best on MI355X at
-// 16384^2), halved (down to 8) until there are about two waves per wave
+// 16384^2 in FP64; in FP32 128 rows are within 1% there and 5% slower at
+// 8192^2), halved (down to 8) until there are about two waves per wave
 // slot of the chip: 4096 waves in FP64 (2 waves per SIMD), 8192 in FP32
-// (4 per SIMD), the best measured at 4096^2.  LF_FUSED_ROWS (a power of
-// two, 4..4096) overrides it.  The launch shape never changes the result.
+// (4 per SIMD), the best measured at 4096^2.  LF_FUSED_ROWS (4..4096)
+// overrides it.  The launch shape never changes the result.
 static int fused_rows(int nx, int ny, int esize) {
   const int tiles_x = (nx + kFTileW - 1) / kFTileW;
   const long long min_waves = esize == 8 ? 4096 : 8192;
@@ -419,7 +420,7 @@ static int fused_rows(int nx, int ny, int esize) {
   while (r > 8 && (long long)tiles_x * ((ny + r - 1) / r) < min_waves) r /= 2;
   if (const char* env = getenv("LF_FUSED_ROWS")) {
     const int v = atoi(env);
-    if (v >= 4 && v <= 4096 && (v & (v - 1)) == 0) r = v;
+    if (v >= 4 && v <= 4096) r = v;
   }
   return r > ny ? ny : r;
 }
