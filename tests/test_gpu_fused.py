@@ -65,7 +65,7 @@ def test_single_pass_step_bitwise_limiters(beta, dtype):
     assert np.array_equal(to_host(out), to_host(_two_stage(S, d, dt)))
 
 
-@pytest.mark.parametrize("rows", ["4", "8", "64", "4096"])
+@pytest.mark.parametrize("rows", ["4", "5", "8", "37", "64", "4096"])
 def test_single_pass_strip_heights(rows, monkeypatch):
     """The strip height changes the launch shape only."""
     monkeypatch.setenv("LF_FUSED_ROWS", rows)
