@@ -66,12 +66,21 @@ def test_step_in_place_and_free_stream():
     d = to_dev(U)
     S.step(d, d, dt)  # in place
     assert np.all(rel_linf(to_host(d), oracle.step(P, U, dt)) <= TOL64)
-    # uniform state: bitwise fixed point
+    # uniform state: bitwise fixed point, in both precisions and with
+    # uniform mass fractions
     Uu = workloads.prim_to_cons(1.4, np.full((90, 200), 0.7), 0.3, -0.2, 1.1)
-    d = to_dev(Uu)
-    o = S.empty_state()
-    S.step(d, o, dt)
-    assert np.array_equal(to_host(o), Uu)
+    for dtype in ("f64", "f32"):
+        Sd = solver_for(cfg, dtype)
+        d = to_dev(Uu, dtype)
+        o = Sd.empty_state()
+        Sd.step(d, o, dt)
+        assert np.array_equal(to_host(o), to_host(d)), dtype
+    Uf = np.concatenate([Uu, 0.7 * np.array([0.25, 0.5])[:, None, None] * np.ones((2, 90, 200))])
+    Sf = solver_for(dict(cfg, ns=2))
+    d = to_dev(Uf)
+    o = Sf.empty_state()
+    Sf.step(d, o, dt)
+    assert np.array_equal(to_host(o), Uf)
 
 
 @pytest.mark.parametrize("bc", BCS)
