@@ -20,7 +20,10 @@
 // would read).  Transmissive: the corrector sees ghost rows and columns of
 // U* as copies of the edge row or column, as the two-stage path does when
 // it reads U* with clamped indices; the predictor never computes ghost rows,
-// and a ghost lane reads U* from the lane of the edge column.
+// and a ghost lane reads U* from the lane of the edge column.  Ghost rows
+// (a strip of a larger grid, lf_step_halo): the 4 rows beyond each end of
+// the strip come from caller buffers, and U* of the rows beyond the ends is
+// computed from them as a periodic strip computes it from wrapped rows.
 #include <stdlib.h>
 
 #include "lf_internal.h"
