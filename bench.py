@@ -457,8 +457,9 @@ def traffic_entry(n, key):
 
 def profile_pass(L, W, n):
     """Fixed short sequence for rocprofv3: each stage kernel of both
-    precisions (and the FP64 one with one mass fraction) a few times, then
-    a plain device copy of known size."""
+    precisions (and the FP64 one with one mass fraction) a few times, the
+    adjoint step at 4096^2 in both precisions, then a plain device copy of
+    known size."""
     import torch
     for flag, tdt, k in ((L.LF_F64, torch.float64, 0), (L.LF_F32, torch.float32, 0), (L.LF_F64, torch.float64, 1)):
         U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=k)
@@ -469,6 +470,17 @@ def profile_pass(L, W, n):
             time_single_pass(S, U, 5)
         torch.cuda.synchronize()
         del U, S
+        torch.cuda.empty_cache()
+    # the adjoint kernels at the adjoint benchmark's size
+    for flag, tdt in ((L.LF_F64, torch.float64), (L.LF_F32, torch.float32)):
+        U, cfg = W.kelvin_helmholtz_torch(4096, device="cuda", dtype=tdt)
+        S = make_solver(L, cfg, flag)
+        dt = S.dt(U)
+        lam, out = torch.ones_like(U), torch.empty_like(U)
+        for _ in range(3):
+            S.adjoint_step(U, dt, lam, out)
+        torch.cuda.synchronize()
+        del U, S, lam, out
         torch.cuda.empty_cache()
     # plain copies of known size for the counter calibration: 1 GiB read +
     # 1 GiB written per launch, by torch's copy kernel and by the runtime's
