@@ -64,17 +64,18 @@ def test_strips_equal_whole_grid(heights, bcx, dtype):
     assert torch.equal(_strips_step(cfg, U, dt, heights, dtype), ref)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ns", [1, 2, 4])
-def test_strips_equal_whole_grid_fractions(ns):
+def test_strips_equal_whole_grid_fractions(ns, dtype):
     import torch
     nx, ny = 121, 40
     cfg = _cfg(nx, ny, 1, ns=ns)
-    U = to_dev(workloads.random_state_fractions(nx, ny, ns, seed=ns))
-    S = solver_for(cfg)
+    U = to_dev(workloads.random_state_fractions(nx, ny, ns, seed=ns), dtype)
+    S = solver_for(cfg, dtype)
     dt = S.dt(U)
     ref = S.empty_state()
     S.step(U, ref, dt)
-    assert torch.equal(_strips_step(cfg, U, dt, [13, 2, 25], "f64"), ref)
+    assert torch.equal(_strips_step(cfg, U, dt, [13, 2, 25], dtype), ref)
 
 
 def test_strips_equal_whole_grid_conservative_reconstruction():
