@@ -423,7 +423,14 @@ def cpu_baseline(W, n=2048, min_seconds=10.0, max_steps=400):
         steps += 1
     sec = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n * n * steps / sec, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "host_cpu": model, "host_logical_cpus": os.cpu_count(),
             "sample": f"Kelvin-Helmholtz {n}^2, {steps} FP64 Heun steps at fixed dt ({sec:.1f} s), "
                       f"OMP_NUM_THREADS={cores}"}
 
