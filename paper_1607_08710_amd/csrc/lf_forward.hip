@@ -422,46 +422,58 @@ __device__ __forceinline__ Acc acc_merge(Acc a, Acc b) {
 
 constexpr int kMaxFields = 4 + kMaxSpecies;
 
-template <int NT>
-__device__ void block_merge(Acc (&v)[kMaxFields], int nf, Acc (*sh)[NT]) {
-  for (int f = 0; f < nf; ++f) sh[f][threadIdx.x] = v[f];
+// The field count is a template parameter so that the accumulators stay in
+// registers (a runtime-indexed array would live in scratch memory).
+template <int NT, int NF>
+__device__ void block_merge(Acc (&v)[NF], Acc (*sh)[NT]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) sh[f][threadIdx.x] = v[f];
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
-      for (int f = 0; f < nf; ++f) sh[f][threadIdx.x] = acc_merge(sh[f][threadIdx.x], sh[f][threadIdx.x + w]);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sh[f][threadIdx.x] = acc_merge(sh[f][threadIdx.x], sh[f][threadIdx.x + w]);
     __syncthreads();
   }
-  for (int f = 0; f < nf; ++f) v[f] = sh[f][0];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = sh[f][0];
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void totals_partial_kernel(const T* __restrict__ U, long long plane, int nf,
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void totals_partial_kernel(const T* __restrict__ U, long long plane,
                                                              double* __restrict__ part) {
-  __shared__ Acc sh[kMaxFields][256];
-  Acc v[kMaxFields];
-  for (int f = 0; f < kMaxFields; ++f) v[f] = Acc{0, 0};
+  __shared__ Acc sh[NF][256];
+  Acc v[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = Acc{0, 0};
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride)
-    for (int f = 0; f < nf; ++f) v[f] = acc_add(v[f], double(U[f * plane + q]));
-  block_merge<256>(v, nf, sh);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = acc_add(v[f], double(U[f * plane + q]));
+  block_merge<256, NF>(v, sh);
   if (threadIdx.x == 0)
-    for (int f = 0; f < nf; ++f) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
       part[(blockIdx.x * kMaxFields + f) * 2 + 0] = v[f].s;
       part[(blockIdx.x * kMaxFields + f) * 2 + 1] = v[f].c;
     }
 }
 
-__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ part, int nblk, int nf,
-                                                           double area, Ctl* ctl) {
-  __shared__ Acc sh[kMaxFields][256];
-  Acc v[kMaxFields];
-  for (int f = 0; f < kMaxFields; ++f) v[f] = Acc{0, 0};
+template <int NF>
+__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ part, int nblk, double area,
+                                                           Ctl* ctl) {
+  __shared__ Acc sh[NF][256];
+  Acc v[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = Acc{0, 0};
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-    for (int f = 0; f < nf; ++f)
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
       v[f] = acc_merge(v[f], Acc{part[(b * kMaxFields + f) * 2], part[(b * kMaxFields + f) * 2 + 1]});
-  block_merge<256>(v, nf, sh);
+  block_merge<256, NF>(v, sh);
   if (threadIdx.x == 0)
-    for (int f = 0; f < nf; ++f) ctl->totals[f] = (v[f].s + v[f].c) * area;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) ctl->totals[f] = (v[f].s + v[f].c) * area;
 }
 
 // ---- host launchers -----------------------------------------------------------
@@ -576,19 +588,31 @@ hipError_t launch_ctl_step(Ctl* ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NF>
+static void launch_totals_nf(const Grid& g, const void* U, long long plane, double* part, int nblk, Ctl* ctl,
+                             hipStream_t s) {
+  if (g.dtype == 0)
+    hipLaunchKernelGGL((totals_partial_kernel<double, NF>), dim3(nblk), dim3(256), 0, s,
+                       static_cast<const double*>(U), plane, part);
+  else
+    hipLaunchKernelGGL((totals_partial_kernel<float, NF>), dim3(nblk), dim3(256), 0, s,
+                       static_cast<const float*>(U), plane, part);
+  hipLaunchKernelGGL((totals_final_kernel<NF>), dim3(1), dim3(256), 0, s, part, nblk, g.dx * g.dy, ctl);
+}
+
 hipError_t launch_totals(const Grid& g, const Layout& L, const void* U, void* ws, hipStream_t s) {
   const long long plane = (long long)g.nx * g.ny;
   char* w = static_cast<char*>(ws);
   double* part = reinterpret_cast<double*>(w + L.partials);
   Ctl* ctl = reinterpret_cast<Ctl*>(w + L.ctl);
-  if (g.dtype == 0)
-    hipLaunchKernelGGL(totals_partial_kernel<double>, dim3(L.totals_blocks), dim3(256), 0, s,
-                       static_cast<const double*>(U), plane, 4 + g.ns, part);
-  else
-    hipLaunchKernelGGL(totals_partial_kernel<float>, dim3(L.totals_blocks), dim3(256), 0, s,
-                       static_cast<const float*>(U), plane, 4 + g.ns, part);
-  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, s, part, L.totals_blocks, 4 + g.ns,
-                     g.dx * g.dy, ctl);
+  static_assert(kMaxSpecies == 4, "one instantiation per field count");
+  switch (4 + g.ns) {
+    case 4: launch_totals_nf<4>(g, U, plane, part, L.totals_blocks, ctl, s); break;
+    case 5: launch_totals_nf<5>(g, U, plane, part, L.totals_blocks, ctl, s); break;
+    case 6: launch_totals_nf<6>(g, U, plane, part, L.totals_blocks, ctl, s); break;
+    case 7: launch_totals_nf<7>(g, U, plane, part, L.totals_blocks, ctl, s); break;
+    default: launch_totals_nf<8>(g, U, plane, part, L.totals_blocks, ctl, s); break;
+  }
   return hipGetLastError();
 }
 
