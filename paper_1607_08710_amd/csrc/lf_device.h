@@ -157,15 +157,30 @@ __device__ __forceinline__ Prim<T> rec_vars(T q0, T q1, T q2, T q3, T gm1) {
 // library accepts beta = 0 or 1 <= beta <= 2.  With bs = b sign(a), a
 // negative bs (ab < 0) makes the result negative before the max with 0,
 // so one expression also covers the ab <= 0 branch.  The result carries
-// the sign of a.  In FP32, max(0, min(lo, hi)) is the median of (0, lo,
-// hi), one instruction, since hi = max(|a|, bs) is never negative.
+// the sign of a.
+//
+// FP32 has a median-of-three instruction, and there the limiter is
+// med3(t, a, beta b) with t = med3(0, beta a, b), four instructions.  For
+// a, b > 0 and a <= b: t = min(beta a, b), which lies between a and
+// beta b, so the result is t, the max-min's value (its other minimum is
+// a); for b < a: t = b, the smallest of the three, so the result is
+// min(a, beta b), again the max-min's value.  Negative a, b mirror this
+// (the rounded products are odd in their argument).  For ab < 0, t = 0
+// lies between a and beta b, and for a zero argument, or beta = 0, t and
+// one of a, beta b are 0: the result is 0 in every such case.  So both
+// forms give the same value, bit for bit, on every input the library
+// accepts; only the sign of a zero result can differ.
 template <typename T>
 __device__ __forceinline__ T sweby(T a, T b, T beta) {
-  const T bs = copysign(T(1), a) * b;
-  const T aa = fabs(a);
-  const T lo = beta * fmin(aa, bs), hi = fmax(aa, bs);
-  if constexpr (sizeof(T) == 4) return copysign(__builtin_amdgcn_fmed3f(0.0f, lo, hi), a);
-  else return copysign(fmax(fmin(lo, hi), T(0)), a);
+  if constexpr (sizeof(T) == 4) {
+    const float t = __builtin_amdgcn_fmed3f(0.0f, beta * a, b);
+    return __builtin_amdgcn_fmed3f(t, a, beta * b);
+  } else {
+    const T bs = copysign(T(1), a) * b;
+    const T aa = fabs(a);
+    const T lo = beta * fmin(aa, bs), hi = fmax(aa, bs);
+    return copysign(fmax(fmin(lo, hi), T(0)), a);
+  }
 }
 
 // Value and partial derivatives of eq. (sweby) in one pass, with the
