@@ -160,21 +160,21 @@ __device__ __forceinline__ Prim<T> rec_vars(T q0, T q1, T q2, T q3, T gm1) {
 // the sign of a.
 //
 // FP32 has a median-of-three instruction, and there the limiter is
-// med3(t, a, beta b) with t = med3(0, beta a, b), four instructions.  For
-// a, b > 0 and a <= b: t = min(beta a, b), which lies between a and
-// beta b, so the result is t, the max-min's value (its other minimum is
-// a); for b < a: t = b, the smallest of the three, so the result is
-// min(a, beta b), again the max-min's value.  Negative a, b mirror this
-// (the rounded products are odd in their argument).  For ab < 0, t = 0
-// lies between a and beta b, and for a zero argument, or beta = 0, t and
-// one of a, beta b are 0: the result is 0 in every such case.  So both
-// forms give the same value, bit for bit, on every input the library
-// accepts; only the sign of a zero result can differ.
+// med3(beta m, a, b) with m = med3(0, a, b) = minmod(a, b), three
+// instructions.  For a, b > 0 and a <= b: m = a and beta a >= a, so the
+// median is min(beta a, b); the max-min's other minimum, min(a, beta b),
+// is a, so its value is min(beta a, b) as well; b < a is the same with a
+// and b swapped.  Negative a, b mirror this (the rounded products are odd
+// in their argument), and for ab <= 0, m = 0 and the median of (0, a, b)
+// is 0.  So for beta >= 1 both forms give the same value, bit for bit;
+// only the sign of a zero result can differ.  For beta = 0 the FP32 form
+// returns minmod(a, b), not 0: the kernels then weight every slope by
+// h = 0 in the face values (face_plus, face_minus), so no slope is used.
 template <typename T>
 __device__ __forceinline__ T sweby(T a, T b, T beta) {
   if constexpr (sizeof(T) == 4) {
-    const float t = __builtin_amdgcn_fmed3f(0.0f, beta * a, b);
-    return __builtin_amdgcn_fmed3f(t, a, beta * b);
+    const float m = __builtin_amdgcn_fmed3f(0.0f, a, b);
+    return __builtin_amdgcn_fmed3f(beta * m, a, b);
   } else {
     const T bs = copysign(T(1), a) * b;
     const T aa = fabs(a);
@@ -371,18 +371,19 @@ __device__ __forceinline__ Prim<T> slope(const Prim<T>& dm, const Prim<T>& dp, T
           sweby(dp.p, dm.p, beta)};
 }
 
-// w + s/2 in the x-face frame (u normal) or the y-face frame (v normal).
+// w + h s (face_plus) and w - h s (face_minus) in the x-face frame (u
+// normal) or the y-face frame (v normal).  The weight h is 1/2, or 0 for
+// beta = 0: then every face takes its cell's value (first order) whatever
+// sweby() returned.
 template <typename T, bool YFACE>
-__device__ __forceinline__ FaceState<T> face_plus(const Prim<T>& w, const Prim<T>& s) {
-  T h = T(0.5);
+__device__ __forceinline__ FaceState<T> face_plus(const Prim<T>& w, const Prim<T>& s, T h) {
   T r = fma(h, s.r, w.r), u = fma(h, s.u, w.u), v = fma(h, s.v, w.v), p = fma(h, s.p, w.p);
   if constexpr (YFACE) return {r, v, u, p};
   else return {r, u, v, p};
 }
 template <typename T, bool YFACE>
-__device__ __forceinline__ FaceState<T> face_minus(const Prim<T>& w, const Prim<T>& s) {
-  T h = T(-0.5);
-  T r = fma(h, s.r, w.r), u = fma(h, s.u, w.u), v = fma(h, s.v, w.v), p = fma(h, s.p, w.p);
+__device__ __forceinline__ FaceState<T> face_minus(const Prim<T>& w, const Prim<T>& s, T h) {
+  T r = fma(-h, s.r, w.r), u = fma(-h, s.u, w.u), v = fma(-h, s.v, w.v), p = fma(-h, s.p, w.p);
   if constexpr (YFACE) return {r, v, u, p};
   else return {r, u, v, p};
 }

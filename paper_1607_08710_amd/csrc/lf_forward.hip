@@ -30,6 +30,7 @@ struct StageArgs {
   int blocks_x, blocks, blocks_pad;
   long long plane;
   T gamma, gm1, inv_gm1, beta, idx, idy, kxy;  // kxy = dx / dy
+  T h;  // weight of a slope in a face value: 1/2, or 0 for beta = 0
   double rdx;  // 1 / dx, for dt / dx
   double dt;
   int dt_dev;
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
   const double dtx = dt * a.rdx;
   const int nx = a.nx, ny = a.ny;
   const long long plane = a.plane;
-  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta;
+  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, h = a.h;
 
   const T* __restrict__ I0 = a.in;
   const T* __restrict__ I1 = I0 + plane;
@@ -167,8 +168,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     Prim<T> s_b = slope(d_lo, d_mid, beta);
     Sg0 = slope(d_mid, sub(W1, W0), beta);
     bool gl;
-    Gf0 = face_flux(face_prim<CONS>(face_plus<T, true>(wb, s_b), gm1),
-                    face_prim<CONS>(face_minus<T, true>(W0, Sg0), gm1), gam, igm1, gl);
+    Gf0 = face_flux(face_prim<CONS>(face_plus<T, true>(wb, s_b, h), gm1),
+                    face_prim<CONS>(face_minus<T, true>(W0, Sg0, h), gm1), gam, igm1, gl);
     if constexpr (NS > 0) {
       const Frac<T, NS> ya = fractions(qa), yb = fractions(qb);
       Y0 = fractions(q0);
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
       for (int s = 0; s < NS; ++s) {
         const T sb = sweby(Y0.v[s] - yb.v[s], yb.v[s] - ya.v[s], beta);
         Sy0.v[s] = sweby(Y1.v[s] - Y0.v[s], Y0.v[s] - yb.v[s], beta);
-        Gy0.v[s] = Gf0.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? sb : Sy0.v[s], gl ? yb.v[s] : Y0.v[s]);
+        Gy0.v[s] = Gf0.f0 * fma(gl ? h : -h, gl ? sb : Sy0.v[s], gl ? yb.v[s] : Y0.v[s]);
       }
     }
   }
@@ -203,8 +204,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const Prim<T> dlo = sub(wo1, wo);
     so1 = slope(dlo, sub(wn, wo1), beta);
     bool gl;
-    G = face_flux(face_prim<CONS>(face_plus<T, true>(wo, so), gm1),
-                  face_prim<CONS>(face_minus<T, true>(wo1, so1), gm1), gam, igm1, gl);
+    G = face_flux(face_prim<CONS>(face_plus<T, true>(wo, so, h), gm1),
+                  face_prim<CONS>(face_minus<T, true>(wo1, so1, h), gm1), gam, igm1, gl);
 
     // x: slopes of row o from lane neighbours, flux through face c+1/2
     const Prim<T> wr1 = shl1(wo);       // w_{c+1}
@@ -213,8 +214,8 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     const Prim<T> sx = slope(dxm, dxp, beta);
     const Prim<T> sx1 = shl1(sx);       // sigma_{c+1}
     bool fl;
-    const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(wo, sx), gm1),
-                                face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1, fl);
+    const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(wo, sx, h), gm1),
+                                face_prim<CONS>(face_minus<T, false>(wr1, sx1, h), gm1), gam, igm1, fl);
     const Flux<T> Fm = shr1(F);         // flux through face c-1/2
 
     // R = (F_{c+1/2} - F_{c-1/2})/dx + (G_{o+1/2} - G_{o-1/2})/dy, eq. (11),
@@ -237,12 +238,12 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       syo1.v[s] = sweby(yn.v[s] - yo1.v[s], yo1.v[s] - yo.v[s], beta);
-      gy.v[s] = G.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? syo.v[s] : syo1.v[s], gl ? yo.v[s] : yo1.v[s]);
+      gy.v[s] = G.f0 * fma(gl ? h : -h, gl ? syo.v[s] : syo1.v[s], gl ? yo.v[s] : yo1.v[s]);
       const T yr1 = shl1(yo.v[s]);
       const T dp = yr1 - yo.v[s];
       const T sxs = sweby(dp, shr1(dp), beta);
       const T sxs1 = shl1(sxs);
-      const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? yo.v[s] : yr1);
+      const T fy = F.f0 * fma(fl ? h : -h, fl ? sxs : sxs1, fl ? yo.v[s] : yr1);
       bs[s] = fma(gy.v[s] - gyp.v[s], a.kxy, fy - shr1(fy));
     }
 
@@ -499,6 +500,7 @@ static hipError_t launch_stage_t(const Grid& g, const void* in, const void* base
   a.gm1 = T(g.gamma - 1.0);
   a.inv_gm1 = T(1.0 / (g.gamma - 1.0));
   a.beta = T(g.beta);
+  a.h = T(g.beta == 0.0 ? 0.0 : 0.5);
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.kxy = T(g.dx / g.dy);

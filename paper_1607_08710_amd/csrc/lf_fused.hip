@@ -49,6 +49,7 @@ struct FusedArgs {
   int blocks_x, blocks, blocks_pad;
   long long plane;
   T gamma, gm1, inv_gm1, beta, idx, idy, kxy;
+  T h;         // weight of a slope in a face value: 1/2, or 0 for beta = 0
   double rdx;  // 1 / dx, for dt / dx
   double dt;
   int dt_dev, reduce;
@@ -93,7 +94,7 @@ struct Win {
 // Window of row a from the rows a-2 .. a+1.
 template <bool CONS, int NS, typename T>
 __device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const RowV<T, NS>& rb,
-                                                   const RowV<T, NS>& r0, const RowV<T, NS>& r1, T beta,
+                                                   const RowV<T, NS>& r0, const RowV<T, NS>& r1, T beta, T h,
                                                    T gam, T gm1, T igm1) {
   Win<T, NS> W;
   const Prim<T> d_mid = sub(r0.w, rb.w);
@@ -101,15 +102,15 @@ __device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const 
   W.d1 = sub(r1.w, r0.w);
   W.s0 = slope(d_mid, W.d1, beta);
   bool gl;
-  W.g = face_flux(face_prim<CONS>(face_plus<T, true>(rb.w, s_b), gm1),
-                  face_prim<CONS>(face_minus<T, true>(r0.w, W.s0), gm1), gam, igm1, gl);
+  W.g = face_flux(face_prim<CONS>(face_plus<T, true>(rb.w, s_b, h), gm1),
+                  face_prim<CONS>(face_minus<T, true>(r0.w, W.s0, h), gm1), gam, igm1, gl);
   W.w0 = r0.w;
   W.w1 = r1.w;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const T sb = sweby(r0.y.v[s] - rb.y.v[s], rb.y.v[s] - ra.y.v[s], beta);
     W.sy0.v[s] = sweby(r1.y.v[s] - r0.y.v[s], r0.y.v[s] - rb.y.v[s], beta);
-    W.gy.v[s] = W.g.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? sb : W.sy0.v[s], gl ? rb.y.v[s] : r0.y.v[s]);
+    W.gy.v[s] = W.g.f0 * fma(gl ? h : -h, gl ? sb : W.sy0.v[s], gl ? rb.y.v[s] : r0.y.v[s]);
   }
   W.y0 = r0.y;
   W.y1 = r1.y;
@@ -124,7 +125,7 @@ __device__ __forceinline__ Win<T, NS> prime_window(const RowV<T, NS>& ra, const 
 // branch).  The difference w1 - w0 is the one formed a row earlier (the
 // same value, when it is recomputed).
 template <bool CONS, int NS, typename T>
-__device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn, T beta, T gam, T gm1, T igm1,
+__device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn, T beta, T h, T gam, T gm1, T igm1,
                                            T kxy, T (&r)[4 + NS]) {
   const Prim<T> dn = sub(rn.w, W.w1);
   Prim<T> d1;
@@ -132,15 +133,15 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
   else d1 = sub(W.w1, W.w0);
   const Prim<T> s1 = slope(d1, dn, beta);
   bool gl, fl;
-  const Flux<T> G = face_flux(face_prim<CONS>(face_plus<T, true>(W.w0, W.s0), gm1),
-                              face_prim<CONS>(face_minus<T, true>(W.w1, s1), gm1), gam, igm1, gl);
+  const Flux<T> G = face_flux(face_prim<CONS>(face_plus<T, true>(W.w0, W.s0, h), gm1),
+                              face_prim<CONS>(face_minus<T, true>(W.w1, s1, h), gm1), gam, igm1, gl);
   const Prim<T> wr1 = shl1(W.w0);
   const Prim<T> dxp = sub(wr1, W.w0);
   const Prim<T> dxm = shr1(dxp);
   const Prim<T> sx = slope(dxm, dxp, beta);
   const Prim<T> sx1 = shl1(sx);
-  const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(W.w0, sx), gm1),
-                              face_prim<CONS>(face_minus<T, false>(wr1, sx1), gm1), gam, igm1, fl);
+  const Flux<T> F = face_flux(face_prim<CONS>(face_plus<T, false>(W.w0, sx, h), gm1),
+                              face_prim<CONS>(face_minus<T, false>(wr1, sx1, h), gm1), gam, igm1, fl);
   const Flux<T> Fm = shr1(F);
   r[0] = fma(G.f0 - W.g.f0, kxy, F.f0 - Fm.f0);
   r[1] = fma(G.f2 - W.g.f2, kxy, F.f1 - Fm.f1);
@@ -149,12 +150,12 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const T sy1 = sweby(rn.y.v[s] - W.y1.v[s], W.y1.v[s] - W.y0.v[s], beta);
-    const T gy = G.f0 * fma(gl ? T(0.5) : T(-0.5), gl ? W.sy0.v[s] : sy1, gl ? W.y0.v[s] : W.y1.v[s]);
+    const T gy = G.f0 * fma(gl ? h : -h, gl ? W.sy0.v[s] : sy1, gl ? W.y0.v[s] : W.y1.v[s]);
     const T yr1 = shl1(W.y0.v[s]);
     const T dp = yr1 - W.y0.v[s];
     const T sxs = sweby(dp, shr1(dp), beta);
     const T sxs1 = shl1(sxs);
-    const T fy = F.f0 * fma(fl ? T(0.5) : T(-0.5), fl ? sxs : sxs1, fl ? W.y0.v[s] : yr1);
+    const T fy = F.f0 * fma(fl ? h : -h, fl ? sxs : sxs1, fl ? W.y0.v[s] : yr1);
     r[4 + s] = fma(gy - W.gy.v[s], kxy, fy - shr1(fy));
     W.sy0.v[s] = sy1;
     W.gy.v[s] = gy;
@@ -203,7 +204,7 @@ void fused_step_kernel(FusedArgs<T> a) {
   const long long P = a.plane;
   const double dt = a.dt_dev ? a.ctl->dt : a.dt;
   const double dtx = dt * a.rdx;
-  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, kxy = a.kxy, idx = a.idx;
+  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, h = a.h, kxy = a.kxy, idx = a.idx;
 
   const T* __restrict__ I0 = a.in;
   auto load_row = [&](int row, T (&q)[NF]) {
@@ -271,7 +272,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     put_n(plo, q0);
     put_n(plo + 1, q1);
     PW = prime_window<CONS, NS>(row_vars<CONS, NS>(qa, gm1), row_vars<CONS, NS>(qb, gm1),
-                                row_vars<CONS, NS>(q0, gm1), row_vars<CONS, NS>(q1, gm1), beta, gam, gm1, igm1);
+                                row_vars<CONS, NS>(q0, gm1), row_vars<CONS, NS>(q1, gm1), beta, h, gam, gm1, igm1);
   }
   int pr = plo;  // next U* row to produce
   // U* of the last two rows produced (conservative, this lane's column):
@@ -288,7 +289,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     for (int f = 0; f < NF; ++f) QA[f] = QB[f];
     if (pr + 4 <= nlast) load_row(pr + 4, QB);
     T bal[NF];  // flux balances
-    window_row<CONS, NS>(PW, rn, beta, gam, gm1, igm1, kxy, bal);
+    window_row<CONS, NS>(PW, rn, beta, h, gam, gm1, igm1, kxy, bal);
     const int sn = nslot(pr);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -325,7 +326,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     while (pr <= r) produce();
     cw[k] = star_row();
   }
-  Win<T, NS> CW = prime_window<CONS, NS>(cw[0], cw[1], cw[2], cw[3], beta, gam, gm1, igm1);
+  Win<T, NS> CW = prime_window<CONS, NS>(cw[0], cw[1], cw[2], cw[3], beta, h, gam, gm1, igm1);
   // U* (conservative) of the rows the corrector combines next: row o in C0,
   // row o+1 in C1
   T C0[NF], C1[NF];
@@ -349,7 +350,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     if (fresh) produce();
     const RowV<T, NS> rn = star_row();  // U* row rmap(o+2), the newest produced
     T bal[NF];
-    window_row<CONS, NS>(CW, rn, beta, gam, gm1, igm1, kxy, bal);
+    window_row<CONS, NS>(CW, rn, beta, h, gam, gm1, igm1, kxy, bal);
     const int sn = nslot(o);
     T u[NF];
 #pragma unroll
@@ -452,6 +453,7 @@ static hipError_t launch_fused_t(const Grid& g, const void* in, void* out, void*
   a.gm1 = T(g.gamma - 1.0);
   a.inv_gm1 = T(1.0 / (g.gamma - 1.0));
   a.beta = T(g.beta);
+  a.h = T(g.beta == 0.0 ? 0.0 : 0.5);
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.kxy = T(g.dx / g.dy);
