@@ -94,6 +94,39 @@ __device__ __forceinline__ float shl1(float v) {
   return __int_as_float(shl1_i(__float_as_int(v)));
 }
 
+// ---- row access: uniform row address plus the lane's byte offset ----------
+//
+// A row's address is the same in every lane and is held in scalar
+// registers; each lane adds a 32-bit byte offset, which the global load and
+// store instructions take as a separate operand, so no per-lane 64-bit
+// address is formed.  The empty asm statements emit no instruction; they
+// keep the compiler from folding the lane's loop-invariant offset into a
+// per-lane 64-bit base outside the row loop (it would then add every row's
+// offset with vector instructions).  lane_offset() re-forms the offset for
+// one row (one register move, shared by the row's fields); ld_lane() and
+// st_lane() take the row address, which must be uniform, in scalar
+// registers.
+
+#define LF_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ unsigned lane_offset(const T* row, unsigned boff) {
+  asm("" : "+v"(boff) : "s"(row));
+  return boff;
+}
+template <typename T>
+__device__ __forceinline__ T ld_lane(const T* row, unsigned boff) {
+  const LF_GLOBAL char* g = (const LF_GLOBAL char*)row;
+  asm("" : "+s"(g));
+  return *(const LF_GLOBAL T*)(g + boff);
+}
+template <typename T>
+__device__ __forceinline__ void st_lane(T* row, unsigned boff, T v) {
+  LF_GLOBAL char* g = (LF_GLOBAL char*)row;
+  asm("" : "+s"(g));
+  *(LF_GLOBAL T*)(g + boff) = v;
+}
+
 // ---- reciprocal and reciprocal square root -------------------------------
 //
 // FP64: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by two

@@ -207,6 +207,9 @@ void fused_step_kernel(FusedArgs<T> a) {
   const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, h = a.h, kxy = a.kxy, idx = a.idx;
 
   const T* __restrict__ I0 = a.in;
+  // byte offsets of this lane's column in a row: loads (cm) and stores (c,
+  // stored only where it lies in the grid)
+  const unsigned lboff = unsigned(cm) * sizeof(T), sboff = unsigned(c) * sizeof(T);
   auto load_row = [&](int row, T (&q)[NF]) {
     if constexpr (BCY == kBcGhost) {
       // the strip's rows, or the ghost rows beyond its ends (every row
@@ -223,13 +226,15 @@ void fused_step_kernel(FusedArgs<T> a) {
         pl = (long long)kGhostRows * nx;
         r = row - ny;
       }
-      const int off = r * nx + cm;
+      const T* rp = src + (long long)r * nx;
+      const unsigned bo = lane_offset(rp, lboff);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) q[f] = src[f * pl + off];
+      for (int f = 0; f < NF; ++f) q[f] = ld_lane(rp + f * pl, bo);
     } else {
-      const int off = map_index<BCY>(row, ny) * nx + cm;
+      const T* rp = I0 + (long long)map_index<BCY>(row, ny) * nx;
+      const unsigned bo = lane_offset(rp, lboff);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) q[f] = I0[f * P + off];
+      for (int f = 0; f < NF; ++f) q[f] = ld_lane(rp + f * P, bo);
     }
   };
 
@@ -300,9 +305,10 @@ void fused_step_kernel(FusedArgs<T> a) {
     // U* of the strip's own rows, when asked for (halo rows belong to the
     // neighbouring strips)
     if (a.ustar && out_lane && pr >= y0 && pr < y1) {
-      const long long so = (long long)pr * nx + c;
+      T* rp = a.ustar + (long long)pr * nx;
+      const unsigned bo = lane_offset(rp, sboff);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) a.ustar[f * P + so] = S1[f];
+      for (int f = 0; f < NF; ++f) st_lane(rp + f * P, bo, S1[f]);
     }
     ++pr;
   };
@@ -356,9 +362,10 @@ void fused_step_kernel(FusedArgs<T> a) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) u[f] = combine<kCorrector>(C0[f], my_n[sn][f][lane], bal[f], dtx, idx);
     if (out_lane) {
-      const long long so = (long long)o * nx + c;
+      T* rp = a.out + (long long)o * nx;
+      const unsigned bo = lane_offset(rp, sboff);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) a.out[f * P + so] = u[f];
+      for (int f = 0; f < NF; ++f) st_lane(rp + f * P, bo, u[f]);
     }
     // next row's U*: row o+1 (C1), and row o+2 (just produced, S1) behind it
 #pragma unroll
