@@ -47,3 +47,31 @@ def test_single_pass_valu_count(kernel_asm):
     got = {8: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIdLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"),
            4: _main_loop_valu(asm, "_ZN2lf17fused_step_kernelIfLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE")}
     assert got == bench.VALU_OPS_PER_CELL, got
+
+
+def _registers(asm):
+    """Kernel name -> (VGPRs, spilled VGPRs, spilled SGPRs), from the code
+    object metadata of the assembly."""
+    out = {}
+    for blk in asm.split("  - .agpr_count")[1:]:
+        name = re.search(r"\.name:\s+(\S+)", blk).group(1)
+        out[name] = tuple(int(re.search(r"\.%s:\s+(\d+)" % k, blk).group(1))
+                          for k in ("vgpr_count", "vgpr_spill_count", "sgpr_spill_count"))
+    return out
+
+
+def test_kernel_registers(kernel_asm):
+    """No kernel spills VGPRs to scratch memory, except the FP64 strip step
+    (ghost rows) with four mass fractions (two registers).  (SGPR spills go
+    to VGPR lanes, not to memory, and are not counted.)  The FP32
+    single-pass step of the benchmark fits five waves per SIMD (at most 96
+    VGPRs), the FP64 one two (at most 256)."""
+    regs = {}
+    for src in ("lf_forward.hip", "lf_fused.hip", "lf_adjoint.hip"):
+        regs.update(_registers(kernel_asm[src]))
+    assert len(regs) > 200
+    spills = {k: v[1] for k, v in regs.items() if v[1]}
+    assert spills == {"_ZN2lf17fused_step_kernelIdLi0ELi2ELi4ELb0EEEvNS_9FusedArgsIT_EE": 2,
+                      "_ZN2lf17fused_step_kernelIdLi1ELi2ELi4ELb0EEEvNS_9FusedArgsIT_EE": 2}, spills
+    assert regs["_ZN2lf17fused_step_kernelIfLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"][0] <= 96
+    assert regs["_ZN2lf17fused_step_kernelIdLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"][0] <= 256
