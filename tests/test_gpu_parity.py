@@ -200,6 +200,30 @@ def test_step_f32(shape, bc):
     assert np.all(err <= 2e-6), err
 
 
+@pytest.mark.parametrize("beta", [0.0, 1.0, 2.0])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
+def test_step_f32_limiters(beta, bc):
+    """FP32 at the limiter's end points.  For beta = 0 the FP32 limiter
+    returns minmod(a, b) (its median form holds for beta >= 1 only) and the
+    face values weight every slope by 0: the step must be the oracle's
+    first-order step, which a slope left in would miss by far more than
+    the bar."""
+    cfg = _cfg(130, 70, *bc, beta=beta)
+    U = workloads.random_state(130, 70, seed=303 + int(10 * beta) + bc[0])
+    U32 = U.astype(np.float32).astype(np.float64)
+    P = oracle_params(cfg)
+    rc, dt = oracle.dt(P, U32)
+    S = solver_for(cfg, "f32")
+    out = S.empty_state()
+    S.step(to_dev(U32, "f32"), out, dt)
+    err = rel_l1(to_host(out), oracle.step(P, U32, dt))
+    assert np.all(err <= 2e-6), err
+    R = S.empty_state()
+    S.residual(to_dev(U32, "f32"), R)
+    err = rel_l1(to_host(R), oracle.residual(P, U32))
+    assert np.all(err <= 2e-5), err
+
+
 def test_residual_vjp_f64():
     for bc in BCS:
         cfg = _cfg(70, 45, *bc)

@@ -55,9 +55,13 @@ def test_step_conservative_f64(beta, bc):
     assert np.array_equal(to_host(out), to_host(ref))
 
 
-def test_step_conservative_f32():
-    cfg = _cfg(130, 70, 1, 0)
-    U = workloads.random_state(130, 70, seed=71)
+@pytest.mark.parametrize("beta", [0.0, 1.5, 2.0])
+def test_step_conservative_f32(beta):
+    """FP32, the limiter's end points included: for beta = 0 the FP32
+    limiter returns minmod, and only the zero weight of the slopes in the
+    face values makes the step first order."""
+    cfg = _cfg(130, 70, 1, 0, beta)
+    U = workloads.random_state(130, 70, seed=71 + int(10 * beta))
     U32 = U.astype(np.float32).astype(np.float64)
     P = oracle_params(cfg)
     rc, dt = oracle.dt(P, U32)

@@ -59,9 +59,13 @@ def test_step_species_f64(ns, bc, beta):
 
 
 @pytest.mark.parametrize("ns", [1, 3])
-def test_step_species_f32(ns):
-    cfg = _cfg(130, 70, 1, 0, ns)
-    U = workloads.random_state_fractions(130, 70, ns, seed=50 + ns)
+@pytest.mark.parametrize("beta", [0.0, 1.5, 2.0])
+def test_step_species_f32(ns, beta):
+    """FP32, the limiter's end points included: for beta = 0 the FP32
+    limiter returns minmod, and only the zero weight of the slopes in the
+    face values (the fractions' as well) makes the step first order."""
+    cfg = _cfg(130, 70, 1, 0, ns, beta)
+    U = workloads.random_state_fractions(130, 70, ns, seed=50 + ns + int(10 * beta))
     U32 = U.astype(np.float32).astype(np.float64)
     P = oracle_params(cfg)
     rc, dt = oracle.dt(P, U32)
