@@ -431,15 +431,20 @@ void fused_step_kernel(FusedArgs<T> a) {
 // Strip height of the fused kernel: 128 rows in FP64, 64 in FP32 (each
 // strip recomputes 4 rows of U* for its halo; measured best on MI355X at
 // 16384^2 in FP64; in FP32 128 rows are within 1% there and 5% slower at
-// 8192^2), halved (down to 8) until there are about two waves per wave
-// slot of the chip: 4096 waves in FP64 (2 waves per SIMD), 8192 in FP32
-// (4 per SIMD), the best measured at 4096^2.  LF_FUSED_ROWS (4..4096)
-// overrides it.  The launch shape never changes the result.
+// 8192^2).  FP64 halves it to 64 rows while the launch has fewer than
+// 16384 waves (at 8192^2 64 rows are 2.5-3% faster than 128).  Then it is
+// halved (down to 8) until there are about two waves per wave slot of the
+// chip: 4096 waves in FP64 (2 waves per SIMD), 8192 in FP32, the best
+// measured at 4096^2.  LF_FUSED_ROWS (4..4096) overrides it.  The launch
+// shape never changes the result.
 static int fused_rows(int nx, int ny, int esize) {
-  const int tiles_x = (nx + kFTileW - 1) / kFTileW;
-  const long long min_waves = esize == 8 ? 4096 : 8192;
+  const long long tiles_x = (nx + kFTileW - 1) / kFTileW;
+  auto waves = [&](int r) { return tiles_x * ((ny + r - 1) / r); };
   int r = esize == 8 ? 128 : 64;
-  while (r > 8 && (long long)tiles_x * ((ny + r - 1) / r) < min_waves) r /= 2;
+  if (esize == 8)
+    while (r > 64 && waves(r) < 16384) r /= 2;
+  const long long min_waves = esize == 8 ? 4096 : 8192;
+  while (r > 8 && waves(r) < min_waves) r /= 2;
   if (const char* env = getenv("LF_FUSED_ROWS")) {
     const int v = atoi(env);
     if (v >= 4 && v <= 4096) r = v;
