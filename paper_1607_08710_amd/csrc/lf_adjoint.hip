@@ -340,11 +340,12 @@ static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, con
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.dt = dt;
-  // strip height: 32 rows, halved (to 8) until ~8k waves exist;
+  // strip height: 32 rows, halved (to 8) until ~16k waves exist (the best
+  // measured at 4096^2, 16 rows, and 8192^2, 32 rows, in both precisions);
   // LF_ADJ_ROWS (a power of two, 4..4096) overrides it (launch shape only)
   const int tiles_x = (g.nx + kAdjTileW - 1) / kAdjTileW;
   int r = 32;
-  while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < 8192) r /= 2;
+  while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < 16384) r /= 2;
   if (const char* env = getenv("LF_ADJ_ROWS")) {
     const int v = atoi(env);
     if (v >= 4 && v <= 4096 && (v & (v - 1)) == 0) r = v;
