@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     // Mass fractions: reconstructed like the primitive variables and
     // carried by the face mass flux from its upwind side, (rho_A u*) y_A.
     // The upwind face value is one fma whose operands are selected
-    // (y + s/2 from the left cell or y - s/2 from the right one): written
+    // (y + h s from the left cell or y - h s from the right one): written
     // as a select of two fmas, the compiler may branch on the side and
     // move the lane shift of the right cell's slope into one arm, where
     // the lanes of the other arm are inactive and read as zero.
