@@ -641,12 +641,15 @@ Grid make_grid(int nx, int ny, double dx, double dy, double gamma, double cfl, d
   // Rows per wave (strip height).  Longer strips amortise the 4 halo rows
   // and the strip prologue; shorter strips keep the rows that the resident
   // waves stream through close together, which the memory system rewards.
-  // Measured on MI355X at 16384^2: 32 rows is best in FP64, 64 in FP32.
-  // Halve it until at least ~8k waves (8 per SIMD) exist.
+  // Measured on MI355X: 32 rows is best in FP64 and 64 in FP32 at 16384^2,
+  // 16 and 32 at 8192^2, 16 in both at 4096^2 (2-9% faster stages there
+  // than 32 rows): halve it, down to 16, until at least 64k waves (FP64)
+  // or 32k (FP32) exist.
   // LF_STRIP_ROWS (a power of two, 4..4096) overrides the choice; it
   // changes the launch shape only, never the result.
   int r = dtype == 0 ? 32 : 64;
-  while (r > 16 && (long long)g.tiles_x * ((ny + r - 1) / r) < 8192) r /= 2;
+  const long long min_waves = dtype == 0 ? 65536 : 32768;
+  while (r > 16 && (long long)g.tiles_x * ((ny + r - 1) / r) < min_waves) r /= 2;
   if (const char* env = getenv("LF_STRIP_ROWS")) {
     const int v = atoi(env);
     if (v >= 4 && v <= 4096 && (v & (v - 1)) == 0) r = v;
