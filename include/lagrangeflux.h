@@ -166,10 +166,10 @@ int lf_stage(lf_ctx *ctx, int stage, const void *in, const void *base, void *out
  * count, and (if dts_out != NULL) the dt of the first min(steps,
  * dts_capacity) steps into the host array dts_out.  Returns
  * LF_ERR_NONPHYSICAL if the initial state or any state produced is
- * non-physical (the state of that step is left in U).  Without mass
- * fractions every step is the single-pass kernel of lf_step, alternating
- * between U and the workspace's U* buffer; an odd step count ends with one
- * device copy back into U. */
+ * non-physical (the state of that step is left in U).  Every step, with
+ * or without mass fractions, is the single-pass kernel of lf_step,
+ * alternating between U and the workspace's U* buffer; an odd step count
+ * ends with one device copy back into U. */
 int lf_advance(lf_ctx *ctx, void *U, double t0, double t_end, int64_t max_steps,
                void *ws, void *stream, double *t_out, int64_t *steps_out,
                double *dts_out, int64_t dts_capacity);

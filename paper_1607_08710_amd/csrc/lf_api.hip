@@ -198,7 +198,6 @@ int lf_advance(lf_ctx* ctx, void* U, double t0, double t_end, int64_t max_steps,
   // the device marks the loop done return at once, so the result is in
   // buffer (steps % 2) and is copied back to U at the end when that is the
   // workspace.
-  const bool fused = true;
   void* buf[2] = {U, us};
   long long launched = 0;
   long long done_steps = 0;
@@ -211,14 +210,9 @@ int lf_advance(lf_ctx* ctx, void* U, double t0, double t_end, int64_t max_steps,
     if (batch > (long long)max_steps - done_steps) batch = (long long)max_steps - done_steps;
     if (batch < 1) batch = 1;
     for (long long k = 0; k < batch && e == hipSuccess; ++k) {
-      if (fused) {
-        e = lf::launch_fused_step(ctx->g, buf[launched & 1], buf[(launched + 1) & 1], nullptr, 0.0, ctl, true,
-                                  true, s);
-        ++launched;
-      } else {
-        e = lf::launch_stage(ctx->g, lf::kPredictor, U, nullptr, us, 0.0, ctl, true, false, s);
-        if (e == hipSuccess) e = lf::launch_stage(ctx->g, lf::kCorrector, us, U, U, 0.0, ctl, true, true, s);
-      }
+      e = lf::launch_fused_step(ctx->g, buf[launched & 1], buf[(launched + 1) & 1], nullptr, 0.0, ctl, true,
+                                true, s);
+      ++launched;
       if (e == hipSuccess) e = lf::launch_ctl_step(ctl, s);
     }
     if (e != hipSuccess) return LF_ERR_HIP;
@@ -242,7 +236,7 @@ int lf_advance(lf_ctx* ctx, void* U, double t0, double t_end, int64_t max_steps,
     }
     done_steps = h.step;
   }
-  if (fused && (h.step & 1)) {
+  if (h.step & 1) {
     e = hipMemcpyAsync(U, us, ctx->state_bytes, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return LF_ERR_HIP;

@@ -53,8 +53,12 @@ class LagrangeFluxRollout(torch.autograd.Function):
     def backward(ctx, gN: torch.Tensor):
         solver, dts, C = ctx.solver, ctx.dts, ctx.C
         ckpts = ctx.saved_tensors
-        lam = gN.contiguous().to(solver.torch_dtype)
         N = len(dts)
+        # a copy: the adjoint steps below ping-pong between lam and lam_next,
+        # and the caller's output gradient must come back unchanged
+        lam = gN.to(solver.torch_dtype, copy=True).contiguous()
+        if N == 0:  # U_N = U_0
+            return lam, None, None, None
         nseg = len(ckpts)
         lam_next = torch.empty_like(lam)
         for s in reversed(range(nseg)):

@@ -1,0 +1,73 @@
+"""CPU tests of the checkpointed rollout's bookkeeping (rollout.py) with a
+stand-in solver whose step is the linear map U -> a U: the rollout's
+gradient is then a^N times the output gradient, whatever the checkpoint
+spacing.  No GPU and no HIP library are involved: the stand-in implements
+the solver methods the rollout calls (step, step_save, stage,
+adjoint_step_ustar) with torch CPU ops."""
+import pytest
+import torch
+
+from paper_1607_08710_amd.rollout import rollout
+
+A = 0.9
+
+
+class LinearSolver:
+    torch_dtype = torch.float64
+
+    def __init__(self, shape):
+        self.shape = shape
+        self.calls = {"step": 0, "step_save": 0, "stage": 0, "adjoint": 0}
+
+    def empty_state(self):
+        return torch.empty(self.shape, dtype=self.torch_dtype)
+
+    def step(self, Un, Unp1, dt):
+        self.calls["step"] += 1
+        torch.mul(Un, A, out=Unp1)
+
+    def step_save(self, Un, Unp1, Ustar, dt):
+        self.calls["step_save"] += 1
+        torch.mul(Un, A, out=Unp1)
+        Ustar.copy_(Un)
+
+    def stage(self, stage, inp, out, dt, base=None, reduce=False):
+        assert stage == 1
+        self.calls["stage"] += 1
+        out.copy_(inp)
+
+    def adjoint_step_ustar(self, Un, Ustar, dt, lam_np1, lam_n):
+        self.calls["adjoint"] += 1
+        assert lam_n.data_ptr() != lam_np1.data_ptr()
+        torch.mul(lam_np1, A, out=lam_n)
+
+
+@pytest.mark.parametrize("steps,ckpt", [(1, 20), (4, 20), (7, 3), (20, 20), (41, 20)])
+def test_gradient_and_output_gradient_untouched(steps, ckpt):
+    shape = (4, 3, 5)
+    S = LinearSolver(shape)
+    x = torch.rand(shape, dtype=torch.float64, requires_grad=True)
+    UN = rollout(x, S, [1e-3] * steps, ckpt_every=ckpt)
+    assert torch.allclose(UN, x.detach() * A ** steps, rtol=1e-15, atol=0)
+    v = torch.rand(shape, dtype=torch.float64)
+    v_before = v.clone()
+    (g,) = torch.autograd.grad(UN, x, grad_outputs=v)
+    # the caller's output gradient comes back unchanged and unshared
+    assert torch.equal(v, v_before)
+    assert g.data_ptr() != v.data_ptr()
+    assert torch.allclose(g, v_before * A ** steps, rtol=1e-14, atol=0)
+    assert S.calls["adjoint"] == steps
+
+
+def test_empty_rollout():
+    shape = (4, 2, 2)
+    S = LinearSolver(shape)
+    x = torch.rand(shape, dtype=torch.float64, requires_grad=True)
+    UN = rollout(x, S, [], ckpt_every=20)
+    assert torch.equal(UN, x.detach()) and UN.data_ptr() != x.data_ptr()
+    v = torch.rand(shape, dtype=torch.float64)
+    v_before = v.clone()
+    (g,) = torch.autograd.grad(UN, x, grad_outputs=v)
+    assert torch.equal(g, v_before) and torch.equal(v, v_before)
+    assert g.data_ptr() != v.data_ptr()
+    assert sum(S.calls.values()) == 0
