@@ -56,6 +56,11 @@ VALU_OPS_PER_CELL = {8: 1723 / 3, 4: 1240 / 3}
 KERNEL_SOURCES = ["paper_1607_08710_amd/csrc/lf_forward.hip", "paper_1607_08710_amd/csrc/lf_fused.hip",
                   "paper_1607_08710_amd/csrc/lf_device.h", "paper_1607_08710_amd/csrc/lf_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kh16384.json")
+ADJ_SOURCES = KERNEL_SOURCES + ["paper_1607_08710_amd/csrc/lf_adjoint.hip"]
+ADJ_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_adjoint_kh4096.json")
+# Bytes per cell of a full gradient step (forward step + its recompute +
+# lf_adjoint_step, each at the two-pass design's compulsory traffic)
+FULL_GRADIENT_BYTES = {8: 608, 4: 304}
 METRIC = "cell-updates/s per step (FP64 vs FP32, % HBM roofline) + adjoint step/s at 4096^2"
 
 
@@ -63,9 +68,9 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -344,6 +349,29 @@ def copy_bandwidth(nbytes=4 << 30, reps=10):
     return 2 * nbytes / sec / 1e9
 
 
+def add_bandwidth(nbytes=2 << 30, reps=10):
+    """HBM bandwidth of a plain element-wise c = a + b over float64 arrays of
+    nbytes each (torch's add kernel): two streams read and one written per
+    element, the read-heavy pattern of a corrector stage (which reads two
+    states and writes one).  Bytes read + written per second."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    torch.add(a, b, out=c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 3 * nbytes / sec / 1e9
+
+
 def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
     """Bare lf_adjoint_step rate, and the full gradient (forward + recompute
     + adjoint) of a steps-long rollout with checkpoints every ckpt steps."""
@@ -408,91 +436,136 @@ def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
     return res
 
 
-def cpu_baseline(W, n=2048, min_seconds=10.0, max_steps=400):
-    """FP64 oracle on the same Kelvin-Helmholtz recipe at n^2, as many steps
-    as fit in ~min_seconds (at least 2), on this host's cores."""
-    import oracle
-    U, cfg = W.kelvin_helmholtz(n)
-    P = oracle.Params(cfg["nx"], cfg["ny"], cfg["dx"], cfg["dy"], cfg["gamma"], cfg["cfl"], cfg["beta"],
-                      cfg["bc_x"], cfg["bc_y"])
-    rc, dt = oracle.dt(P, U)
-    t0 = time.perf_counter()
-    steps = 0
-    while steps < 2 or (time.perf_counter() - t0 < min_seconds and steps < max_steps):
-        U = oracle.step(P, U, dt)
-        steps += 1
-    sec = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+def _host_cpu():
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n * n * steps / sec, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "host_cpu": model, "host_logical_cpus": os.cpu_count(),
-            "sample": f"Kelvin-Helmholtz {n}^2, {steps} FP64 Heun steps at fixed dt ({sec:.1f} s), "
+    return model
+
+
+def oracle_rate(U, cfg, min_seconds, min_steps=1, max_steps=400):
+    """FP64 oracle Heun steps of state U at its fixed CFL dt, as many as fit
+    in ~min_seconds (at least min_steps): (cell-updates/s, steps, seconds)."""
+    import oracle
+    P = oracle.Params(cfg["nx"], cfg["ny"], cfg["dx"], cfg["dy"], cfg["gamma"], cfg["cfl"], cfg["beta"],
+                      cfg["bc_x"], cfg["bc_y"])
+    rc, dt = oracle.dt(P, U)
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < min_steps or (time.perf_counter() - t0 < min_seconds and steps < max_steps):
+        U = oracle.step(P, U, dt)
+        steps += 1
+    sec = time.perf_counter() - t0
+    return cfg["nx"] * cfg["ny"] * steps / sec, steps, sec
+
+
+def cpu_baseline(W, n=16384, rows=None, min_seconds=10.0):
+    """The FP64 oracle on the benchmark's own workload, the Kelvin-Helmholtz
+    state at n^2 (or its bottom `rows` rows), at least one full step, as
+    many as fit in ~min_seconds, on this host's OpenMP threads."""
+    U, cfg = W.kelvin_helmholtz(n, rows=rows)
+    rate, steps, sec = oracle_rate(U, cfg, min_seconds)
+    del U
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    what = f"{n}^2 (full grid)" if rows is None else f"{n} x {rows} (its bottom {rows} rows, periodic)"
+    return {"value": rate, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "host_cpu": _host_cpu(), "host_logical_cpus": os.cpu_count(),
+            "sample": f"Kelvin-Helmholtz {what}, {steps} FP64 Heun step(s) at fixed dt ({sec:.1f} s), "
                       f"OMP_NUM_THREADS={cores}"}
 
 
-def cpu_per_core(n=1024, min_seconds=4.0):
+def cpu_planned(W, vortex_n=4096, quadrant_n=8192, min_seconds=3.0):
+    """The oracle on bounded samples of the isentropic vortex at 4096^2 and
+    the four-quadrant problem at 8192^2 (the timing workloads of the
+    oracle's plan), all threads: a few full-grid steps of each."""
+    out = {}
+    U, cfg = W.vortex(vortex_n)
+    rate, steps, sec = oracle_rate(U, cfg, min_seconds)
+    out["vortex"] = {"value": rate, "n": vortex_n, "steps": steps, "seconds": sec}
+    del U
+    U, cfg = W.four_quadrant(quadrant_n)
+    rate, steps, sec = oracle_rate(U, cfg, min_seconds)
+    out["four_quadrant"] = {"value": rate, "n": quadrant_n, "steps": steps, "seconds": sec}
+    del U
+    out["unit"] = "cell-updates/s"
+    out["cores"] = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return out
+
+
+def cpu_per_core(n=16384, rows=1024, min_seconds=4.0):
     """The oracle on one thread (the per-core figure the paper compares
-    with), in a child process started with OMP_NUM_THREADS=1 (OpenMP reads
-    it at start-up); the child touches no GPU."""
+    with) on the bottom `rows` rows of the benchmark grid, in a child
+    process started with OMP_NUM_THREADS=1 (OpenMP reads it at start-up);
+    the child touches no GPU."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
     out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-only", "--cpu-n", str(n),
-                          "--cpu-seconds", str(min_seconds)], env=env, capture_output=True, text=True,
-                         timeout=600, check=True)
+                          "--cpu-rows", str(rows), "--cpu-seconds", str(min_seconds)], env=env,
+                         capture_output=True, text=True, timeout=900, check=True)
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
-def traffic_entry(n, key):
-    """HBM bytes per launch of one kernel (key in the counter record, e.g.
-    corrector_f64_bytes) from the committed rocprofv3 counter summary, or
-    None when absent or taken from other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_entry(n, key, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """A per-launch figure of one kernel (key in a committed counter record,
+    e.g. corrector_f64_bytes) from the rocprofv3 counter summary at path,
+    or None when absent, taken at another grid size or from other kernel
+    sources."""
+    if not os.path.exists(path):
         return None, "no counter summary"
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hash") != kernel_source_hash(sources):
         return None, "kernel changed since the counters were taken"
     if rec.get("n") != n:
         return None, "counters taken at another size"
+    if rec.get(key) is None:
+        return None, "not in the counter summary"
     return rec.get(key), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel"
 
 
-def profile_pass(L, W, n):
-    """Fixed short sequence for rocprofv3: each stage kernel of both
-    precisions (and the FP64 one with one mass fraction) a few times, the
-    adjoint step at 4096^2 in both precisions, then a plain device copy of
-    known size."""
-    import torch
-    for flag, tdt, k in ((L.LF_F64, torch.float64, 0), (L.LF_F32, torch.float32, 0), (L.LF_F64, torch.float64, 1)):
-        U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=k)
-        S = make_solver(L, cfg, flag)
-        S.advance(U, 0.0, math.inf, max_steps=4)  # even: no copy back from the workspace
-        time_stages(S, U, 5)
-        if k == 0:
-            time_single_pass(S, U, 5)
-        torch.cuda.synchronize()
-        del U, S
-        torch.cuda.empty_cache()
-    # the adjoint kernels at the adjoint benchmark's size
-    for flag, tdt in ((L.LF_F64, torch.float64), (L.LF_F32, torch.float32)):
-        U, cfg = W.kelvin_helmholtz_torch(4096, device="cuda", dtype=tdt)
-        S = make_solver(L, cfg, flag)
-        dt = S.dt(U)
-        lam, out = torch.ones_like(U), torch.empty_like(U)
-        for _ in range(3):
-            S.adjoint_step(U, dt, lam, out)
-        torch.cuda.synchronize()
-        del U, S, lam, out
-        torch.cuda.empty_cache()
-    # plain copies of known size for the counter calibration: 1 GiB read +
-    # 1 GiB written per launch, by torch's copy kernel and by the runtime's
-    # device-to-device memcpy
+def adjoint_rooflines(n, adj64, adj32):
+    """lf_adjoint_step (288 / 144 B per cell: U* recomputed, then the two
+    adjoint stages) and the full gradient step (608 / 304 B per cell:
+    forward step, its recompute and the adjoint step) against HBM, from the
+    timed rates; traffic per lf_adjoint_step from the committed counters of
+    its three kernels."""
+    cells = n * n
+    out = {}
+    for name, r, esz in (("f64", adj64, 8), ("f32", adj32, 4)):
+        if r is None:
+            continue
+        b = BYTES_PER_CELL[("adjoint_step", esz)]
+        ach = b * cells * r["lf_adjoint_step_per_s"] / 1e9
+        traffic, src = traffic_entry(n, f"adjoint_step_{name}_bytes", ADJ_TRAFFIC_FILE, ADJ_SOURCES)
+        issued, _ = traffic_entry(n, f"adjoint_step_{name}_valu_wave_instructions", ADJ_TRAFFIC_FILE, ADJ_SOURCES)
+        step = {"bound": "hbm",
+                "kernel": f"lf_adjoint_step (FP{esz * 8}): stage_kernel predictor (U* recomputed) + "
+                          f"adjoint_kernel modes 1 and 2",
+                "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+                "traffic": traffic, "traffic_source": src, "algorithmic_bytes_per_cell": b,
+                "cells_per_launch": cells, "avg_launch_ms": r["lf_adjoint_step_ms"]}
+        if issued:
+            step["issued_valu_lane_instructions_per_cell"] = issued * 64 / cells
+            step["valu_issue_frac"] = issued * 64 * r["lf_adjoint_step_per_s"] / 1e12 / VALU_PEAK_TOPS
+        bf = FULL_GRADIENT_BYTES[esz]
+        achf = bf * cells * r["full_gradient_steps_per_s"] / 1e9
+        full = {"bound": "hbm", "achieved": achf, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achf / HBM_PEAK_GBPS, "algorithmic_bytes_per_cell_step": bf,
+                "steps_per_s": r["full_gradient_steps_per_s"],
+                "steps_per_s_at_roofline": HBM_PEAK_GBPS * 1e9 / (bf * cells)}
+        out[name] = {"lf_adjoint_step": step, "full_gradient": full}
+    return out
+
+
+def _calibration_copies():
+    """Plain copies of known size for the counter calibration: 1 GiB read +
+    1 GiB written per launch, by torch's copy kernel and by the runtime's
+    device-to-device memcpy."""
     import ctypes
+    import torch
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -504,6 +577,47 @@ def profile_pass(L, W, n):
         rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), 1 << 30, 3, stream)
         assert rc == 0, rc
     torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+def _adjoint_profile_steps(L, W, n):
+    """lf_adjoint_step three times in each precision at n^2 (its three
+    kernels: the predictor recompute and the two adjoint stages)."""
+    import torch
+    for flag, tdt in ((L.LF_F64, torch.float64), (L.LF_F32, torch.float32)):
+        U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt)
+        S = make_solver(L, cfg, flag)
+        dt = S.dt(U)
+        lam, out = torch.ones_like(U), torch.empty_like(U)
+        for _ in range(3):
+            S.adjoint_step(U, dt, lam, out)
+        torch.cuda.synchronize()
+        del U, S, lam, out
+        torch.cuda.empty_cache()
+
+
+def profile_pass(L, W, n, which="kernels", adj_n=4096):
+    """Fixed short sequences for rocprofv3.  "kernels": each stage kernel of
+    both precisions (and the FP64 one with one mass fraction) a few times,
+    the single-pass kernel through lf_advance and lf_step, the adjoint step
+    at 4096^2 in both precisions, then plain device copies of known size.
+    "adjoint": the adjoint steps and the copies only."""
+    import torch
+    if which == "kernels":
+        for flag, tdt, k in ((L.LF_F64, torch.float64, 0), (L.LF_F32, torch.float32, 0),
+                             (L.LF_F64, torch.float64, 1)):
+            U, cfg = W.kelvin_helmholtz_torch(n, device="cuda", dtype=tdt, fractions=k)
+            S = make_solver(L, cfg, flag)
+            S.advance(U, 0.0, math.inf, max_steps=4)  # even: no copy back from the workspace
+            time_stages(S, U, 5)
+            if k == 0:
+                time_single_pass(S, U, 5)
+            torch.cuda.synchronize()
+            del U, S
+            torch.cuda.empty_cache()
+    _adjoint_profile_steps(L, W, adj_n)
+    _calibration_copies()
     log("profile pass done")
 
 
@@ -524,17 +638,19 @@ def main():
                          "(profiling runs use one leg so that each kernel runs at one grid size)")
     ap.add_argument("--shards", type=int, default=8)
     ap.add_argument("--vortex-n", type=int, default=4096)
-    ap.add_argument("--cpu-n", type=int, default=2048, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-n", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-rows", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--oracle-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--quadrant-n", type=int, default=8192)
     ap.add_argument("--quadrant-steps", type=int, default=1000)
     ap.add_argument("--species-steps", type=int, default=200)
-    ap.add_argument("--profile-pass", choices=["none", "kernels"], default="none")
+    ap.add_argument("--profile-pass", choices=["none", "kernels", "adjoint"], default="none")
     args = ap.parse_args()
 
     if args.oracle_only:  # child of cpu_per_core(): the oracle alone, no GPU
         import workloads as W
-        print(json.dumps(cpu_baseline(W, n=args.cpu_n, min_seconds=args.cpu_seconds)), flush=True)
+        print(json.dumps(cpu_baseline(W, n=args.cpu_n, rows=args.cpu_rows or None,
+                                      min_seconds=args.cpu_seconds)), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -554,12 +670,12 @@ def main():
     torch.cuda.set_device(0)
     L.lib()
 
-    if args.profile_pass == "kernels":
-        profile_pass(L, W, args.n)
+    if args.profile_pass != "none":
+        profile_pass(L, W, args.n, args.profile_pass, args.adj_n)
         return
 
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
-    f64 = f32 = adj64 = adj32 = roofline = cpu = None
+    f64 = f32 = adj64 = adj32 = roofline = cpu = hbm_roofline = roofline_adjoint = None
     species = roofline_two_stage = recon64 = quadrant = vortex = shard = None
     if "forward" in legs:
         log(f"FP64 Kelvin-Helmholtz {args.n}^2: {args.warmup} warm-up + {args.steps} timed steps")
@@ -577,18 +693,46 @@ def main():
         sp_s = f64["ms_per_step"] / 1e3
         achieved = VALU_OPS_PER_CELL[8] * cells / sp_s / 1e12
         traffic, traffic_src = traffic_entry(args.n, "single_pass_f64_bytes")
+        issued, _ = traffic_entry(args.n, "single_pass_f64_lf_advance_valu_wave_instructions")
         copy_gbps = copy_bandwidth()
-        log(f"device copy {copy_gbps:.0f} GB/s")
+        add_gbps = add_bandwidth()
+        log(f"device copy {copy_gbps:.0f} GB/s, two-read one-write probe {add_gbps:.0f} GB/s")
         roofline = {"bound": "alu",
                     "kernel": "lf::fused_step_kernel<double, 0, 0, 0, false> (FP64 single-pass step, periodic)",
                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_source": traffic_src,
                     "algorithmic_ops_per_cell": VALU_OPS_PER_CELL[8],
-                    "ops": "VALU lane-instructions per cell-step, counted from the kernel's gfx950 assembly",
+                    "ops": "VALU lane-instructions per OUTPUT cell-step: the main loop's instructions per row "
+                           "and lane, counted from the kernel's gfx950 assembly, on the 56 output lanes of "
+                           "each 64-lane wave (halo lanes and strip prologues not counted)",
+                    "peak_definition": "256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz lane-instructions/s (FP64 "
+                                       "add/mul/fma, DPP moves, selects issue at this rate)",
                     "algorithmic_bytes_per_cell": BYTES_PER_CELL[("single_pass", 8)],
                     "hbm_GBps": BYTES_PER_CELL[("single_pass", 8)] * cells / sp_s / 1e9,
+                    "hbm_frac": BYTES_PER_CELL[("single_pass", 8)] * cells / sp_s / 1e9 / HBM_PEAK_GBPS,
                     "cells_per_launch": cells, "avg_launch_ms": f64["ms_per_step"],
-                    "measured_copy_GBps": copy_gbps}
+                    "measured_copy_GBps": copy_gbps, "measured_two_read_one_write_GBps": add_gbps}
+        if issued:
+            # all lanes, halo columns and strip prologues included (SQ_INSTS_VALU x 64)
+            roofline["issued_ops_per_cell"] = issued * 64 / cells
+            roofline["issued_frac"] = issued * 64 / sp_s / 1e12 / VALU_PEAK_TOPS
+        # the metric's "% HBM roofline": cell-updates/s x the compulsory bytes
+        # of the two-pass design (160 B FP64, 80 B FP32 per cell-step) against
+        # 8 TB/s; the single-pass kernel moves 64 / 32 of those bytes
+        hbm_roofline = {"definition": "cell-updates/s x bytes per cell-step of the two-pass design "
+                                      "(predictor R 32 + W 32, corrector R 64 + W 32 in FP64; half in FP32) / "
+                                      "8 TB/s",
+                        "peak_GBps": HBM_PEAK_GBPS}
+        for name, r, esz in (("f64", f64, 8), ("f32", f32, 4)):
+            b = BYTES_PER_CELL[("step", esz)]
+            hbm_roofline[name] = {
+                "bytes_per_cell_step": b,
+                "single_pass": {"cell_updates_per_s": r["value"], "GBps": r["value"] * b / 1e9,
+                                "frac": r["value"] * b / 1e9 / HBM_PEAK_GBPS},
+                "two_stage": {"cell_updates_per_s": r["two_stage"]["value"],
+                              "GBps": r["two_stage"]["value"] * b / 1e9,
+                              "frac": r["two_stage"]["value"] * b / 1e9 / HBM_PEAK_GBPS},
+            }
         # the two-stage design (one kernel per stage) against HBM
         corr_s = f64["corrector_ms"] / 1e3
         ach2 = BYTES_PER_CELL[("corrector", 8)] * cells / corr_s / 1e9
@@ -599,7 +743,9 @@ def main():
                               "frac": ach2 / HBM_PEAK_GBPS, "traffic": traffic2, "traffic_source": traffic_src2,
                               "algorithmic_bytes_per_cell": BYTES_PER_CELL[("corrector", 8)],
                               "cells_per_launch": cells, "avg_launch_ms": f64["corrector_ms"],
-                              "measured_copy_GBps": copy_gbps, "frac_of_measured_copy": ach2 / copy_gbps}
+                              "measured_copy_GBps": copy_gbps, "frac_of_measured_copy": ach2 / copy_gbps,
+                              "measured_two_read_one_write_GBps": add_gbps,
+                              "frac_of_two_read_one_write": ach2 / add_gbps}
     if "species" in legs:
         species = {}
         for k in (1, 2):
@@ -636,13 +782,19 @@ def main():
         log(f"adjoint FP64: {adj64['lf_adjoint_step_per_s']:.1f} lf_adjoint_step/s, "
             f"{adj64['full_gradient_steps_per_s']:.1f} full-gradient steps/s")
         adj32 = adjoint_leg(L, W, args.adj_n, L.LF_F32, args.adj_steps, args.adj_ckpt, 10)
-        log(f"adjoint FP32: {adj32['lf_adjoint_step_per_s']:.1f} lf_adjoint_step/s")
+        log(f"adjoint FP32: {adj32['lf_adjoint_step_per_s']:.1f} lf_adjoint_step/s, "
+            f"{adj32['full_gradient_steps_per_s']:.1f} full-gradient steps/s")
+        roofline_adjoint = adjoint_rooflines(args.adj_n, adj64, adj32)
     if "cpu" in legs and not args.no_cpu_baseline:
         log("CPU oracle baseline")
-        cpu = cpu_baseline(W, min_seconds=args.cpu_seconds)
-        log(f"oracle {cpu['value'] / 1e6:.2f} M cell-updates/s on {cpu['cores']} threads")
-        cpu["one_thread"] = cpu_per_core()
+        cpu_n = args.cpu_n or args.n
+        cpu = cpu_baseline(W, n=cpu_n, min_seconds=args.cpu_seconds)
+        log(f"oracle {cpu['value'] / 1e6:.2f} M cell-updates/s on {cpu['cores']} threads ({cpu['sample']})")
+        cpu["one_thread"] = cpu_per_core(n=cpu_n, rows=min(1024, cpu_n))
         log(f"oracle on one thread {cpu['one_thread']['value'] / 1e6:.2f} M cell-updates/s")
+        cpu["planned_workloads"] = cpu_planned(W)
+        log(f"oracle: vortex {cpu['planned_workloads']['vortex']['value'] / 1e6:.2f} M, four-quadrant "
+            f"{cpu['planned_workloads']['four_quadrant']['value'] / 1e6:.2f} M cell-updates/s")
 
     line = {
         "metric": METRIC,
@@ -662,6 +814,8 @@ def main():
                    "nx": args.n, "ny": args.n, "parallelism": "single GPU"},
         "roofline": roofline,
         "roofline_two_stage": roofline_two_stage,
+        "hbm_roofline": hbm_roofline,
+        "roofline_adjoint": roofline_adjoint,
         "cpu_baseline": cpu,
         "fp64": f64,
         "fp32": f32,

@@ -8,8 +8,9 @@
     (oracle-pinned) FP64 GPU path, plus the diagonal symmetry;
   * adjoint (1024^2 periodic, smooth seeded density, 200 steps, checkpoints
     every 20): gradient of the final-density misfit vs central finite
-    differences along 8 seeded directions (FP64), FP32 gradient vs FP64,
-    multi-step GPU gradient vs the oracle's;
+    differences along 8 seeded directions (FP64 and FP32), the FP32
+    gradient's distance from the FP64 one split into adjoint arithmetic and
+    trajectory, multi-step GPU gradient vs the oracle's;
   * Kelvin-Helmholtz at 16384^2: a sampled step against the oracle, FP32
     vs FP64 over 500 steps;
   * determinism: repeated runs and N steps vs k + (N - k) steps, bitwise.
@@ -215,27 +216,109 @@ def test_adjoint_fd_1024_f64():
         assert err <= 1e-6, (m, err)
 
 
-def test_adjoint_f32_vs_f64_1024():
-    """The misfit gradient is sensitive to last-bit changes of the
-    trajectory: on smooth data the Sweby limiter sits on its |a| = |b|
-    kink, so the one-sided derivatives flip in many cells.  Rounding U0
-    alone to FP32 moves the FP64 gradient by ~5e-4 (relative L2); the FP32
-    path, whose trajectory differs by FP32 rounding every step, lands at
-    ~1.6e-3 after 200 steps.  Bar: 5e-3."""
+def _fp32_trajectory(cfg, U0r, dt, steps):
+    """The FP32 forward trajectory of lf_step_save: the states U^0..U^N and
+    each step's predictor state U*, all kept (1024^2: 6.7 GB)."""
+    S = solver_for(cfg, "f32")
+    X, US = [to_dev(U0r, "f32")], []
+    for _ in range(steps):
+        a, us = S.empty_state(), S.empty_state()
+        S.step_save(X[-1], a, us, dt)
+        X.append(a)
+        US.append(us)
+    return X, US
+
+
+def test_adjoint_f32_gradient_decomposed_1024():
+    """Where the FP32 gradient's distance from the FP64 one comes from.
+
+    The misfit gradient at this workload is sensitive to last-bit changes
+    of the trajectory (reading 16): on smooth data the Sweby limiter sits
+    on its |a| = |b| kink near the density's inflection lines, and there a
+    change of the state by ~1e-6 flips the one-sided derivative the adjoint
+    takes.  The FP32 trajectory differs from the FP64 one by up to 8.7e-6
+    after 200 steps.  So the comparison is split:
+
+      * adjoint arithmetic: the FP32 gradient (rollout) against the FP64
+        adjoint carried along the same FP32 trajectory (its states and U*
+        upcast exactly, FP64 lf_adjoint_step_ustar, which the oracle pins):
+        measured 2.5e-7 relative L2; bar 2e-6, the size of FP32 rounding
+        (1.2e-7) accumulated over 200 steps as a random walk (x sqrt(200));
+      * trajectory: the FP32 gradient's distance from the FP64 gradient
+        (measured 1.670e-3) is the distance of the FP64 adjoint along the
+        FP32 trajectory from the FP64 gradient (measured 1.670e-3), within
+        the arithmetic bar;
+      * the misfit itself within 1e-4 (measured 1.9e-5), and the directional
+        derivatives along the 8 finite-difference directions within 2e-4 of
+        the FP64 ones (measured 3.0e-6 .. 6.5e-5)."""
+    import torch
     n = 1024
     U0, rho_tgt, cfg = workloads.adjoint_case(n)
     rc, dt = oracle.dt(oracle_params(cfg), U0)
+    steps, ckpt = cfg["steps"], cfg["ckpt_every"]
     U0r = U0.astype(np.float32).astype(np.float64)
-    J64, g64 = _gpu_gradient(cfg, U0, rho_tgt, dt, cfg["steps"], cfg["ckpt_every"], "f64")
-    J64r, g64r = _gpu_gradient(cfg, U0r, rho_tgt, dt, cfg["steps"], cfg["ckpt_every"], "f64")
-    J32, g32 = _gpu_gradient(cfg, U0r, rho_tgt, dt, cfg["steps"], cfg["ckpt_every"], "f32")
+    J64, g64 = _gpu_gradient(cfg, U0, rho_tgt, dt, steps, ckpt, "f64")
+    J32, g32 = _gpu_gradient(cfg, U0r, rho_tgt, dt, steps, ckpt, "f32")
+    # FP64 adjoint along the FP32 trajectory
+    X, US = _fp32_trajectory(cfg, U0r, dt, steps)
+    S64 = solver_for(cfg)
+    lam = torch.zeros((4, n, n), dtype=torch.float64, device="cuda")
+    lam[0] = cfg["dx"] * cfg["dy"] * (X[-1][0].double() - to_dev(rho_tgt[None])[0])
+    out = torch.empty_like(lam)
+    for k in reversed(range(steps)):
+        S64.adjoint_step_ustar(X[k].double(), US[k].double(), dt, lam, out)
+        lam, out = out, lam
+    u, v = cfg["u"], cfg["v"]
+    g64_on32 = (lam[0] + u * lam[1] + v * lam[2] + 0.5 * (u * u + v * v) * lam[3]).cpu().numpy()
+    del X, US, lam, out
     nrm = np.linalg.norm(g64)
-    sens = np.linalg.norm(g64r - g64) / nrm
-    rel = np.linalg.norm(g32 - g64) / nrm
-    print(f"FP64 gradient moved by FP32 rounding of U0: {sens:.2e}; FP32 vs FP64 gradient: {rel:.2e} (rel L2)")
-    assert rel <= 5e-3, rel
-    assert sens <= rel  # the FP32 gap exceeds the pure input-rounding effect
-    assert abs(J32 - J64) <= 1e-4 * abs(J64)
+    arith = np.linalg.norm(g32 - g64_on32) / nrm
+    traj = np.linalg.norm(g64_on32 - g64) / nrm
+    total = np.linalg.norm(g32 - g64) / nrm
+    print(f"FP32 gradient vs FP64: {total:.3e}; FP64 adjoint along the FP32 trajectory vs FP64: {traj:.3e}; "
+          f"FP32 vs FP64 adjoint on the same trajectory: {arith:.3e} (relative L2)")
+    assert arith <= 2e-6, arith
+    assert total <= traj + 2e-6, (total, traj)
+    assert abs(J32 - J64) <= 1e-4 * abs(J64), (J32, J64)
+    for m, d in enumerate(workloads.fd_directions(n, count=8)):
+        a32, a64 = float(np.sum(g32 * d)), float(np.sum(g64 * d))
+        assert abs(a32 - a64) <= 2e-4 * abs(a64), (m, a32, a64)
+
+
+def test_adjoint_fd_1024_f32():
+    """FP32 gradient against central differences of the FP32 forward map
+    (200 steps at the frozen dt0, checkpoints every 20) along the 8 seeded
+    directions.  The FP32 state's rounding and the limiter kinks set the
+    step size: measured over eps = 1e-2 .. 1e-4, eps = 1e-3 gives 3.8e-6 ..
+    1.9e-4 relative on the 8 directions (against the FP64 gradient the same
+    differences give 3.8e-6 .. 1.9e-4).  Bar: 5e-4 at eps = 1e-3."""
+    n = 1024
+    U0, rho_tgt, cfg = workloads.adjoint_case(n)
+    rc, dt = oracle.dt(oracle_params(cfg), U0)
+    steps = cfg["steps"]
+    U0r = U0.astype(np.float32).astype(np.float64)
+    J32, g32 = _gpu_gradient(cfg, U0r, rho_tgt, dt, steps, cfg["ckpt_every"], "f32")
+    S = solver_for(cfg, "f32")
+    tgt = to_dev(rho_tgt[None])[0]
+    a, b = S.empty_state(), S.empty_state()
+
+    def Jof(rho0):
+        src = to_dev(workloads.prim_to_cons(cfg["gamma"], rho0, cfg["u"], cfg["v"], cfg["p"]), "f32")
+        for k in range(steps):
+            dst = a if k % 2 == 0 else b
+            S.step(src, dst, dt)
+            src = dst
+        return float(_misfit(src.double(), tgt, cfg["dx"], cfg["dy"]))
+
+    eps = 1e-3
+    worst = 0.0
+    for m, d in enumerate(workloads.fd_directions(n, count=8)):
+        ad = float(np.sum(g32 * d))
+        fd = (Jof(U0r[0] + eps * d) - Jof(U0r[0] - eps * d)) / (2 * eps)
+        err = abs(fd - ad) / abs(ad)
+        worst = max(worst, err)
+        print(f"direction {m + 1}: <grad32, d> = {ad:.8e}, FP32 central FD {fd:.8e}, rel err {err:.2e}")
+    assert worst <= 5e-4, worst
 
 
 def test_adjoint_rollout_vs_oracle():
@@ -284,7 +367,7 @@ def test_kh_16384_sampled_step_and_f32():
     S32.advance(U32, 0.0, np.inf, max_steps=500)
     e1 = ((U32.double() - U).abs().sum(dim=(1, 2)) / U.abs().sum(dim=(1, 2))).cpu().numpy()
     print("KH 16384^2, 500 steps, FP32 vs FP64 rel L1:", e1)
-    assert np.all(e1[[0, 1, 3]] <= 2e-5), e1
+    assert np.all(e1 <= 2e-5), e1
     assert bool(torch.isfinite(U32).all())
 
 

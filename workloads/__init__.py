@@ -136,21 +136,24 @@ def four_quadrant(n: int, *, gamma: float = 1.4, cfl: float = 0.5, beta: float =
 # ---- Kelvin-Helmholtz shear layer -------------------------------------------
 
 def kelvin_helmholtz(n: int, *, gamma: float = 1.4, cfl: float = 0.5, beta: float = 1.5,
-                     steps: int = 500, dtype=np.float64):
+                     steps: int = 500, dtype=np.float64, rows: int | None = None):
     """rho = 2, u = 0.5 for |y - 1/2| < 1/4, else rho = 1, u = -0.5; p = 2.5;
     v = 0.01 sin(4 pi x); periodic [0,1]^2.  The perturbation is
-    deterministic (no random draw)."""
+    deterministic (no random draw).  With ``rows`` = m < n only the bottom
+    m rows of the n^2 grid are built (an n x m state, cfg ny = m, same dx
+    and dy, still periodic: a timing sample of the same rows)."""
     x = cell_centres(n, 0.0, 1.0)
     inner = np.abs(x - 0.5) < 0.25  # along y
     rho_y = np.where(inner, 2.0, 1.0)
     u_y = np.where(inner, 0.5, -0.5)
     v_x = 0.01 * np.sin(4.0 * math.pi * x)
-    U = np.empty((4, n, n), dtype=dtype)
+    m = n if rows is None else int(rows)
+    U = np.empty((4, m, n), dtype=dtype)
     # built row by row to keep peak host memory at one state
-    for j in range(n):
+    for j in range(m):
         rho = np.full(n, rho_y[j])
         U[:, j, :] = prim_to_cons(gamma, rho, u_y[j], v_x, 2.5)
-    cfg = _cfg(n, n, 1.0, 1.0, PERIODIC, PERIODIC, gamma, cfl, beta, steps=steps)
+    cfg = _cfg(n, m, 1.0, m / n, PERIODIC, PERIODIC, gamma, cfl, beta, steps=steps)
     return U, cfg
 
 
