@@ -12,7 +12,7 @@
 // onto its conservative variables.
 //
 // Kernel layout (same idea as the forward stage kernel).  A wave owns 64
-// consecutive columns and produces the middle 56 (the adjoint stencil
+// consecutive columns and produces the middle 58 (the adjoint stencil
 // reaches three cells to each side); it marches up a strip of rows.  Every
 // face is evaluated once per wave: x-faces across the lanes, with the slot
 // contributions moved to their cells by DPP shifts; y-faces one per row,
@@ -31,12 +31,12 @@
 
 namespace lf {
 
-constexpr int kAdjHalo = 4;
+constexpr int kAdjHalo = 3;
 // Waves per block, both precisions.  FP32 (~136 VGPRs) fits three waves
 // per SIMD, twelve per CU: blocks of four fill that, blocks of eight leave
 // room for one block only (eight waves; measured 12% slower at 4096^2).
 constexpr int kAdjWaves = 4;
-constexpr int kAdjTileW = kWave - 2 * kAdjHalo;  // 56 output columns per wave
+constexpr int kAdjTileW = kWave - 2 * kAdjHalo;  // 58 output columns per wave
 
 template <typename T>
 struct AdjArgs {
@@ -48,7 +48,7 @@ struct AdjArgs {
   int rows;      // strip height
   int blocks_x, blocks, blocks_pad;
   long long plane;
-  T gamma, gm1, inv_gm1, beta, idx, idy;
+  T gamma, gm1, inv_gm1, beta, hbeta, idx, idy;
   double dt;
 };
 
@@ -74,20 +74,20 @@ __device__ __forceinline__ P4<T> p4_sel(bool c, const P4<T>& a) {
   return {c ? a.r : T(0), c ? a.u : T(0), c ? a.v : T(0), c ? a.p : T(0)};
 }
 
-// Slope of one cell and its partial derivatives w.r.t. the backward and
-// forward differences, for the four primitive variables.
+// Slope of one cell and half its partial derivatives w.r.t. the backward
+// and forward differences (hda, hdb), for the four primitive variables.
 template <typename T>
 struct SlopeD {
-  P4<T> s, da, db;
+  P4<T> s, hda, hdb;
 };
 
 template <typename T>
-__device__ __forceinline__ SlopeD<T> slope_d(const P4<T>& dm, const P4<T>& dp, T beta) {
+__device__ __forceinline__ SlopeD<T> slope_d(const P4<T>& dm, const P4<T>& dp, T beta, T hbeta) {
   SlopeD<T> o;
-  sweby_all(dm.r, dp.r, beta, o.s.r, o.da.r, o.db.r);
-  sweby_all(dm.u, dp.u, beta, o.s.u, o.da.u, o.db.u);
-  sweby_all(dm.v, dp.v, beta, o.s.v, o.da.v, o.db.v);
-  sweby_all(dm.p, dp.p, beta, o.s.p, o.da.p, o.db.p);
+  sweby_all(dm.r, dp.r, beta, hbeta, o.s.r, o.hda.r, o.hdb.r);
+  sweby_all(dm.u, dp.u, beta, hbeta, o.s.u, o.hda.u, o.hdb.u);
+  sweby_all(dm.v, dp.v, beta, hbeta, o.s.v, o.hda.v, o.hdb.v);
+  sweby_all(dm.p, dp.p, beta, hbeta, o.s.p, o.hda.p, o.hdb.p);
   return o;
 }
 
@@ -119,17 +119,18 @@ __device__ __forceinline__ void face_slots(const P4<T>& w1, const SlopeD<T>& S1,
     lb = {Lb.r, Lb.un, Lb.ut, Lb.p};
     rb = {Rb.r, Rb.un, Rb.ut, Rb.p};
   }
-  // w^L = w1 + phi(w1 - w0, w2 - w1)/2,  w^R = w2 - phi(w2 - w1, w3 - w2)/2
+  // w^L = w1 + phi(w1 - w0, w2 - w1)/2,  w^R = w2 - phi(w2 - w1, w3 - w2)/2;
+  // a1, b1 (a2, b2): half partials of the left (right) cell's slope
   auto one = [&](T l, T r, T a1, T b1, T a2, T b2, T& o0, T& o1, T& o2, T& o3) {
-    o0 = -h * a1 * l;
-    o1 = fma(h * (a1 - b1), l, l) + h * a2 * r;
-    o2 = h * b1 * l + fma(-h * (a2 - b2), r, r);
-    o3 = -h * b2 * r;
+    o0 = -a1 * l;
+    o1 = fma(a1 - b1, l, fma(a2, r, l));
+    o2 = fma(b1, l, fma(b2 - a2, r, r));
+    o3 = -b2 * r;
   };
-  one(lb.r, rb.r, S1.da.r, S1.db.r, S2.da.r, S2.db.r, s0.r, s1.r, s2.r, s3.r);
-  one(lb.u, rb.u, S1.da.u, S1.db.u, S2.da.u, S2.db.u, s0.u, s1.u, s2.u, s3.u);
-  one(lb.v, rb.v, S1.da.v, S1.db.v, S2.da.v, S2.db.v, s0.v, s1.v, s2.v, s3.v);
-  one(lb.p, rb.p, S1.da.p, S1.db.p, S2.da.p, S2.db.p, s0.p, s1.p, s2.p, s3.p);
+  one(lb.r, rb.r, S1.hda.r, S1.hdb.r, S2.hda.r, S2.hdb.r, s0.r, s1.r, s2.r, s3.r);
+  one(lb.u, rb.u, S1.hda.u, S1.hdb.u, S2.hda.u, S2.hdb.u, s0.u, s1.u, s2.u, s3.u);
+  one(lb.v, rb.v, S1.hda.v, S1.hdb.v, S2.hda.v, S2.hdb.v, s0.v, s1.v, s2.v, s3.v);
+  one(lb.p, rb.p, S1.hda.p, S1.hdb.p, S2.hda.p, S2.hdb.p, s0.p, s1.p, s2.p, s3.p);
 }
 
 template <typename T>
@@ -162,50 +163,57 @@ void adjoint_kernel(AdjArgs<T> a) {
   const int y0 = by * a.rows;
   const int y1 = min(y0 + a.rows, ny);
   const long long P = a.plane;
-  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta;
+  const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, hbeta = a.hbeta;
 
+  // rows are addressed as a uniform row pointer (scalar registers) plus
+  // the lane's byte offset (see ld_lane)
+  const unsigned boff = unsigned(cm) * sizeof(T);
   auto load_u = [&](int row) -> P4<T> {
-    const int o = map_index<BCY>(row, ny) * nx + cm;
-    return prim4(a.U[o], a.U[P + o], a.U[2 * P + o], a.U[3 * P + o], gm1);
+    const T* rp = a.U + (long long)map_index<BCY>(row, ny) * nx;
+    const unsigned bo = lane_offset(rp, boff);
+    return prim4(ld_lane(rp, bo), ld_lane(rp + P, bo), ld_lane(rp + 2 * P, bo), ld_lane(rp + 3 * P, bo), gm1);
   };
   // cotangent of R at (row, this lane's column): zero outside a
   // transmissive domain (those cells do not exist)
   auto load_g = [&](int row) -> P4<T> {
     const bool in = (!YT || (row >= 0 && row < ny)) && (!XT || c_in);
-    const int o = map_index<BCY>(row, ny) * nx + cm;
-    P4<T> g = {a.g[o], a.g[P + o], a.g[2 * P + o], a.g[3 * P + o]};
+    const T* rp = a.g + (long long)map_index<BCY>(row, ny) * nx;
+    const unsigned bo = lane_offset(rp, boff);
+    P4<T> g = {ld_lane(rp, bo), ld_lane(rp + P, bo), ld_lane(rp + 2 * P, bo), ld_lane(rp + 3 * P, bo)};
     return p4_sel(in, g);
   };
 
 
   // window: prim rows k-2 .. k+1, g row k-1, y-accumulators rows k-2 ..
   // k+1 (slots rotate every row).  g of the finished row is read again
-  // (from cache).  In FP32 the slope data of row k (value and partials)
-  // are handed to the next iteration, where they are row k-1's, through a
-  // per-wave LDS slot (each lane reads back its own values); in FP64 they
-  // are recomputed instead, since holding them pushes the kernel past 256
-  // registers (measured slower).
-  constexpr bool kCarry = sizeof(T) == 4;
-  __shared__ T scarry[kCarry ? WPB : 1][12][kWave];
-  T(*my_c)[kWave] = scarry[kCarry ? w : 0];
+  // (from cache).  The slope data of row k (value and half partials) are
+  // handed to the next iteration, where they are row k-1's, through a
+  // per-wave LDS slot: each lane reads back its own values, so no barrier
+  // is needed; they are stored as soon as they are formed, so that they
+  // occupy no registers across the rest of the iteration.
+  __shared__ T scarry[WPB][12][kWave];
+  T(*my_c)[kWave] = scarry[w];
   auto put_slope = [&](const SlopeD<T>& S) {
-    const T v[12] = {S.s.r, S.s.u, S.s.v, S.s.p, S.da.r, S.da.u, S.da.v, S.da.p,
-                     S.db.r, S.db.u, S.db.v, S.db.p};
+    const T v[12] = {S.s.r, S.s.u, S.s.v, S.s.p, S.hda.r, S.hda.u, S.hda.v, S.hda.p,
+                     S.hdb.r, S.hdb.u, S.hdb.v, S.hdb.p};
 #pragma unroll
     for (int i = 0; i < 12; ++i) my_c[i][lane] = v[i];
   };
+  // read through a volatile LDS pointer: otherwise the compiler forwards
+  // the stored values and keeps them in registers across the iteration
+  using LdsV = __attribute__((address_space(3))) volatile T;
+  LdsV* my_v = (LdsV*)&scarry[w][0][lane];
   auto get_slope = [&]() {
     SlopeD<T> S;
-    S.s = {my_c[0][lane], my_c[1][lane], my_c[2][lane], my_c[3][lane]};
-    S.da = {my_c[4][lane], my_c[5][lane], my_c[6][lane], my_c[7][lane]};
-    S.db = {my_c[8][lane], my_c[9][lane], my_c[10][lane], my_c[11][lane]};
+    S.s = {my_v[0 * kWave], my_v[1 * kWave], my_v[2 * kWave], my_v[3 * kWave]};
+    S.hda = {my_v[4 * kWave], my_v[5 * kWave], my_v[6 * kWave], my_v[7 * kWave]};
+    S.hdb = {my_v[8 * kWave], my_v[9 * kWave], my_v[10 * kWave], my_v[11 * kWave]};
     return S;
   };
   P4<T> Wm2 = load_u(y0 - 3), Wm1 = load_u(y0 - 2), W0 = load_u(y0 - 1);
   // slope data of row y0-2 (rows y0-3 .. y0-1)
-  if constexpr (kCarry)
-    put_slope(slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
-                      {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta));
+  put_slope(slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
+                    {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta, hbeta));
   P4<T> Gm1 = load_g(y0 - 2);
   const P4<T> Z = {T(0), T(0), T(0), T(0)};
   P4<T> Am2 = Z, Am1 = Z, A0 = Z;  // accumulators for rows k-2, k-1, k
@@ -216,13 +224,12 @@ void adjoint_kernel(AdjArgs<T> a) {
     // new data: prim row k+1, g row k
     const P4<T> W1 = load_u(k + 1);
     const P4<T> Gk = load_g(k);
-    // slopes of rows k-1 (rows k-2, k-1, k; carried in FP32) and k (rows
-    // k-1, k, k+1)
-    const SlopeD<T> Sk1 = kCarry ? get_slope()
-                                 : slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
-                                           {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta);
+    // slopes of rows k-1 (rows k-2, k-1, k; carried) and k (rows k-1, k,
+    // k+1)
+    const SlopeD<T> Sk1 = get_slope();
     const SlopeD<T> Sk = slope_d({W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p},
-                                 {W1.r - W0.r, W1.u - W0.u, W1.v - W0.v, W1.p - W0.p}, beta);
+                                 {W1.r - W0.r, W1.u - W0.u, W1.v - W0.v, W1.p - W0.p}, beta, hbeta);
+    put_slope(Sk);
     P4<T> A1 = Z;  // accumulator of row k+1 starts here
     // ---- y-face k (between rows k-1 and k) ----
     if (!YT || (k >= 0 && k <= ny)) {
@@ -251,11 +258,11 @@ void adjoint_kernel(AdjArgs<T> a) {
       const P4<T> wr1 = p4_shl(Wm2);
       const P4<T> dxp = {wr1.r - Wm2.r, wr1.u - Wm2.u, wr1.v - Wm2.v, wr1.p - Wm2.p};
       const P4<T> dxm = p4_shr(dxp);
-      const SlopeD<T> Sx = slope_d(dxm, dxp, beta);
+      const SlopeD<T> Sx = slope_d(dxm, dxp, beta, hbeta);
       SlopeD<T> Sx1;
       Sx1.s = p4_shl(Sx.s);
-      Sx1.da = p4_shl(Sx.da);
-      Sx1.db = p4_shl(Sx.db);
+      Sx1.hda = p4_shl(Sx.hda);
+      Sx1.hdb = p4_shl(Sx.hdb);
       const P4<T> g1 = p4_shl(Gm2);
       const Flux<T> fb = {(Gm2.r - g1.r) * a.idx, (Gm2.u - g1.u) * a.idx, (Gm2.v - g1.v) * a.idx,
                           (Gm2.p - g1.p) * a.idx};
@@ -269,7 +276,7 @@ void adjoint_kernel(AdjArgs<T> a) {
       s3 = p4_sel(xface, s3);
       // lane c collects slot 0 of the face at lane c+1, slot 1 of its own,
       // slot 2 of lane c-1 and slot 3 of lane c-2
-      P4<T> tx = p4_add(p4_add(p4_shl(s0), s1), p4_add(p4_shr(s2), p4_shr(p4_shr(s3))));
+      P4<T> tx = p4_add(p4_add(p4_shl(s0), s1), p4_shr(p4_add(s2, p4_shr(s3))));
       if constexpr (XT) {
         // ghost columns -1, -2 fold onto column 0; nx, nx+1 onto nx-1
         const P4<T> l1 = p4_shr(tx), l2 = p4_shr(l1);
@@ -288,7 +295,8 @@ void adjoint_kernel(AdjArgs<T> a) {
       vv[3] = gm1 * tot.p;
       const T gg[4] = {Gm2.r, Gm2.u, Gm2.v, Gm2.p};
       T res[4];
-      const int off = r * nx + cm;
+      // output lanes hold columns 0 .. nx-1, where cm = c
+      const long long roff = (long long)r * nx;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if constexpr (MODE == kVjp) {
@@ -296,21 +304,21 @@ void adjoint_kernel(AdjArgs<T> a) {
         } else if constexpr (MODE == kAdjCorr) {
           res[f] = T(0.5 * (double(gg[f]) - a.dt * double(vv[f])));  // mu = (lam - dt v)/2
         } else {
-          const T lam = out_lane ? a.lam[f * P + off] : T(0);  // lam/2 + mu - dt v
+          const T* lp = a.lam + roff + f * P;
+          const T lam = out_lane ? ld_lane(lp, lane_offset(lp, boff)) : T(0);  // lam/2 + mu - dt v
           res[f] = T(0.5 * double(lam) + double(gg[f]) - a.dt * double(vv[f]));
         }
       }
       // stored straight from the lanes: the kernel is bound by arithmetic,
       // and without staging no block barrier ties its waves together
       if (out_lane) {
-        a.out[off] = res[0];
-        a.out[P + off] = res[1];
-        a.out[2 * P + off] = res[2];
-        a.out[3 * P + off] = res[3];
+        T* op = a.out + roff;
+        const unsigned bo = lane_offset(op, boff);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) st_lane(op + f * P, bo, res[f]);
       }
     }
     // slide the window
-    if constexpr (kCarry) put_slope(Sk);
     Wm2 = Wm1;
     Wm1 = W0;
     W0 = W1;
@@ -337,6 +345,7 @@ static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, con
   a.gm1 = T(g.gamma - 1.0);
   a.inv_gm1 = T(1.0 / (g.gamma - 1.0));
   a.beta = T(g.beta);
+  a.hbeta = T(0.5 * g.beta);
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.dt = dt;

@@ -217,13 +217,17 @@ __device__ __forceinline__ T sweby(T a, T b, T beta) {
   }
 }
 
-// Value and partial derivatives of eq. (sweby) in one pass, with the
-// conventions: zero when ab <= 0; min(x, y) follows x when x <= y;
-// max(m1, m2) follows m1 when m1 >= m2.  (a and b share their sign when
-// ab > 0, so the sign factors cancel in the derivatives.)  The value is
+// Value of eq. (sweby) and half its partial derivatives in one pass (a
+// face value is w + phi/2 or w - phi/2, so the adjoint needs the partials
+// of phi/2), with the conventions: zero when ab <= 0; min(x, y) follows x
+// when x <= y; max(m1, m2) follows m1 when m1 >= m2.  (a and b share their
+// sign when ab > 0, so the sign factors cancel in the derivatives.)  The
+// limited value follows one of |a|, beta |b| (through m1) or beta |a|, |b|
+// (through m2): its partial is 1 or beta with respect to the argument it
+// follows and 0 with respect to the other; hbeta = beta / 2.  The value is
 // the max-min form itself; for beta >= 1 it equals sweby() bit for bit.
 template <typename T>
-__device__ __forceinline__ void sweby_all(T a, T b, T beta, T& phi, T& da, T& db) {
+__device__ __forceinline__ void sweby_all(T a, T b, T beta, T hbeta, T& phi, T& hda, T& hdb) {
   const T aa = fabs(a), ab = fabs(b);
   const T ba = beta * aa, bb = beta * ab;
   const T m1 = fmin(aa, bb);   // min(|a|, beta |b|)
@@ -233,10 +237,11 @@ __device__ __forceinline__ void sweby_all(T a, T b, T beta, T& phi, T& da, T& db
   const bool m2a = ba <= ab;   // m2 follows beta |a|
   const bool first = m1 >= m2; // max follows m1
   phi = act ? copysign(fmax(m1, m2), a) : T(0);
-  const bool a1 = act && first && m1a, a2 = act && !first && m2a;
-  const bool b1 = act && first && !m1a, b2 = act && !first && !m2a;
-  da = a1 ? T(1) : (a2 ? beta : T(0));
-  db = b1 ? beta : (b2 ? T(1) : T(0));
+  const bool fa = first ? m1a : m2a;      // follows a
+  const bool unit = first ? m1a : !m2a;   // follows |a| or |b|, unscaled
+  const T hc = unit ? T(0.5) : hbeta;
+  hda = (act && fa) ? hc : T(0);
+  hdb = (act && !fa) ? hc : T(0);
 }
 
 // ---- face flux: Lagrangian HLL solve (eqs. (13)-(14)) + upwind + eq. (12) --
@@ -356,27 +361,42 @@ __device__ __forceinline__ void face_flux_vjp(const FaceState<T>& L, const FaceS
   const T utb = r * fma(Fb.f2, us, Eb * ut);
   const T pb = Eb * inv_gm1;
 
-  // through eqs. (13)-(14)
-  const T BiSa = B * iS * a;
-  const T ab = fma(psb, -(B * iS) * Du, usb * (iS * Dp * ia * ia));
-  const T t1 = Dp * iS2 * ia;  // (p_R - p_L) / (S^2 a)
-  const T rlb = fma(psb, R.r * iS2 * (Dp - R.r * a * Du), usb * fma(-R.r * Du, iS2, t1));
-  const T rrb = fma(psb, -L.r * iS2 * (Dp + L.r * a * Du), usb * fma(L.r * Du, iS2, t1));
+  // through eqs. (13)-(14), with w = (p_R - p_L) / (S a):
+  //   dp*/da = -(rho_L rho_R / S) (u_R - u_L),   du*/da = w / a,
+  //   dp*/drho_L = rho_R (p_R - p_L - rho_R a (u_R - u_L)) / S^2,
+  //   du*/drho_L = (w / S) - rho_R (u_R - u_L) / S^2, and the mirror images
+  const T iSia = iS * ia;
+  const T BiS = B * iS;
+  const T BiSa = BiS * a;
+  const T w = Dp * iSia;
+  const T ab = fma(psb, -BiS * Du, usb * (w * ia));
+  const T t1 = w * iS;
+  const T psbiS2 = psb * iS2, aDu = a * Du, DuiS2 = Du * iS2;
+  const T rlb = fma(psbiS2 * R.r, fma(-R.r, aDu, Dp), usb * fma(-R.r, DuiS2, t1));
+  const T rrb = fma(-(psbiS2 * L.r), fma(L.r, aDu, Dp), usb * fma(L.r, DuiS2, t1));
   const T unlb = fma(psb, BiSa, usb * (L.r * iS));
   const T unrb = fma(-psb, BiSa, usb * (R.r * iS));
-  const T plb = fma(psb, R.r * iS, usb * (iS * ia));
-  const T prb = fma(psb, L.r * iS, -usb * (iS * ia));
-  // a = sqrt(gamma p_s / rho_s)
-  const T dar = ab * (T(-0.5) * a * irs);
-  const T dap = ab * (T(0.5) * gamma * irs * ia);
-  Lb.r = rlb + (aleft ? dar : T(0)) + (left ? rb : T(0));
-  Lb.un = unlb + (left ? unb : T(0));
-  Lb.ut = left ? utb : T(0);
-  Lb.p = plb + (aleft ? dap : T(0)) + (left ? pb : T(0));
-  Rb.r = rrb + (aleft ? T(0) : dar) + (left ? T(0) : rb);
-  Rb.un = unrb + (left ? T(0) : unb);
-  Rb.ut = left ? T(0) : utb;
-  Rb.p = prb + (aleft ? T(0) : dap) + (left ? T(0) : pb);
+  const T plb = fma(psb, R.r * iS, usb * iSia);
+  const T prb = fma(psb, L.r * iS, -usb * iSia);
+  // a = sqrt(gamma p_s / rho_s): da/drho_s = -a / (2 rho_s), da/dp_s =
+  // gamma / (2 rho_s a)
+  const T habr = T(0.5) * ab * irs;
+  const T dar = -habr * a;
+  const T dap = habr * (gamma * ia);
+  // the sound-speed and upwind terms each go to one side: the left
+  // side's share is selected and the right side takes the rest, x - share,
+  // which is exactly x or 0
+  const T darL = aleft ? dar : T(0), dapL = aleft ? dap : T(0);
+  const T rbL = left ? rb : T(0), unbL = left ? unb : T(0);
+  const T utbL = left ? utb : T(0), pbL = left ? pb : T(0);
+  Lb.r = rlb + darL + rbL;
+  Lb.un = unlb + unbL;
+  Lb.ut = utbL;
+  Lb.p = plb + dapL + pbL;
+  Rb.r = rrb + (dar - darL) + (rb - rbL);
+  Rb.un = unrb + (unb - unbL);
+  Rb.ut = utb - utbL;
+  Rb.p = prb + (dap - dapL) + (pb - pbL);
 }
 
 // ---- pieces of a stage row shared by the stage kernels ----------------------
