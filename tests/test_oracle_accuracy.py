@@ -82,13 +82,23 @@ def _vortex_l1(oracle_lib, n):
 
 @pytest.mark.slow
 def test_vortex_second_order(oracle_lib):
+    """Observed L1 orders of the four fields on 64 -> 128 -> 256 -> 512
+    (measured: density 1.45, 1.60, 1.84; the other fields 1.59-1.87).  The
+    order rises towards 2 with resolution: the Sweby limiter clips the
+    smooth extrema of the vortex core to first order, on a region whose
+    share of the L1 error falls as the grid refines.  So the bars are 1.8
+    on the finest pair and 1.55 on 128 -> 256, and the order must grow
+    from pair to pair."""
+    e64 = _vortex_l1(oracle_lib, 64)
     e128 = _vortex_l1(oracle_lib, 128)
     e256 = _vortex_l1(oracle_lib, 256)
     e512 = _vortex_l1(oracle_lib, 512)
+    o0 = np.log2(e64 / e128)
     o1 = np.log2(e128 / e256)
     o2 = np.log2(e256 / e512)
     assert np.all(o1 >= 1.55), o1
     assert np.all(o2 >= 1.8), o2
+    assert np.all(o0 < o1) and np.all(o1 < o2), (o0, o1, o2)
     assert e512[0] < 4e-5
 
 
