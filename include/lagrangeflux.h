@@ -57,7 +57,9 @@ typedef enum {
     LF_ERR_HIP = 2,          /* a HIP runtime call failed                       */
     LF_ERR_NONPHYSICAL = 3,  /* a state with rho <= 0, p <= 0 or a non-finite
                                 value was detected                             */
-    LF_ERR_STATE = 4         /* misuse of the context (e.g. dtype mismatch)     */
+    LF_ERR_STATE = 4,        /* misuse of the context (e.g. dtype mismatch)     */
+    LF_ERR_TOO_LARGE = 5     /* the grid does not fit the fixed scratch of
+                                lf_adjoint_step_noalloc                        */
 } lf_status;
 
 typedef enum { LF_F64 = 0, LF_F32 = 1 } lf_dtype;
@@ -205,6 +207,33 @@ int lf_adjoint_step(lf_ctx *ctx, const void *Un, double dt, const void *lam_np1,
  * context restrictions; lam_n must not overlap Un, Ustar or lam_np1. */
 int lf_adjoint_step_ustar(lf_ctx *ctx, const void *Un, const void *Ustar, double dt,
                           const void *lam_np1, void *lam_n, void *ws, void *stream);
+
+/* Bytes of the library's fixed device scratch used by
+ * lf_adjoint_step_noalloc (64 MiB; one copy per GPU the library runs on,
+ * held until the process ends). */
+#define LF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* lf_adjoint_step for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments without the workspace, same kernels, bitwise
+ * the same lam_n as lf_adjoint_step, async.  U* and mu live in a scratch
+ * array of LF_NOALLOC_SCRATCH_BYTES that the library holds in device
+ * memory (a static device array, not an allocation): nothing is allocated
+ * or freed by the call.  Limit: U* and mu (4 planes each, 256-byte
+ * aligned) must fit the scratch, i.e. nx*ny <= 1048576 cells in FP64 and
+ * <= 2097152 in FP32; larger grids return LF_ERR_TOO_LARGE before any HIP
+ * call.  Same context restrictions as lf_adjoint_step (LF_ERR_ARG);
+ * lam_n must not overlap Un or lam_np1.  stream must belong to the
+ * current device (LF_ERR_ARG otherwise).  The first call on a device
+ * resolves the scratch's device address (hipGetSymbolAddress), which may
+ * load the library's device code there: make that first call outside
+ * stream capture.  All calls on one GPU share its scratch, which keeps
+ * the last call's contents (each call writes U* and mu in full before it
+ * reads them, so nothing needs clearing): calls that may overlap in time
+ * on one GPU -- on different streams, from different threads or contexts
+ * -- race and give undefined results; order them, e.g. on one stream. */
+int lf_adjoint_step_noalloc(lf_ctx *ctx, const void *Un, double dt, const void *lam_np1,
+                            void *lam_n, void *stream);
 
 /* Conservation totals: out[f] = dx*dy * sum_K U_f(K) for the 4 + n_species
  * fields (out has that many entries), summed in FP64 with compensation in

@@ -22,7 +22,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblagrangeflux.so")
 
-LF_OK, LF_ERR_ARG, LF_ERR_HIP, LF_ERR_NONPHYSICAL, LF_ERR_STATE = 0, 1, 2, 3, 4
+LF_OK, LF_ERR_ARG, LF_ERR_HIP, LF_ERR_NONPHYSICAL, LF_ERR_STATE, LF_ERR_TOO_LARGE = 0, 1, 2, 3, 4, 5
+NOALLOC_SCRATCH_BYTES = 64 << 20  # LF_NOALLOC_SCRATCH_BYTES
 LF_F64, LF_F32 = 0, 1
 PERIODIC, TRANSMISSIVE = 0, 1
 LF_MAX_SPECIES = 4
@@ -31,7 +32,7 @@ LF_RECON_PRIMITIVE, LF_RECON_CONSERVATIVE = 0, 1
 # Names exported by the C ABI (include/lagrangeflux.h).
 ABI_FUNCTIONS = ("lf_init", "lf_destroy", "lf_status_string", "lf_dt", "lf_step", "lf_step_save", "lf_step_halo",
                  "lf_stage", "lf_advance", "lf_residual", "lf_residual_vjp", "lf_adjoint_step",
-                 "lf_adjoint_step_ustar", "lf_totals")
+                 "lf_adjoint_step_ustar", "lf_adjoint_step_noalloc", "lf_totals")
 GHOST_ROWS = 4  # LF_GHOST_ROWS: rows a strip needs beyond each end for one step
 
 
@@ -87,9 +88,11 @@ def lib() -> ctypes.CDLL:
         L.lf_residual_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lf_adjoint_step.argtypes = [vp, vp, d, vp, vp, vp, vp]
         L.lf_adjoint_step_ustar.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
+        L.lf_adjoint_step_noalloc.argtypes = [vp, vp, d, vp, vp, vp]
         L.lf_totals.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
         for name in ("lf_init", "lf_dt", "lf_step", "lf_step_save", "lf_step_halo", "lf_stage", "lf_advance",
-                     "lf_residual", "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar", "lf_totals"):
+                     "lf_residual", "lf_residual_vjp", "lf_adjoint_step", "lf_adjoint_step_ustar",
+                     "lf_adjoint_step_noalloc", "lf_totals"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -250,6 +253,16 @@ class Solver:
                                            self._arg(lam_np1, "lam_np1"), self._arg(lam_n, "lam_n"),
                                            ctypes.c_void_p(self.ws.data_ptr()), self._stream()),
                "lf_adjoint_step_ustar")
+
+    def adjoint_step_noalloc(self, Un, dt: float, lam_np1, lam_n):
+        """lf_adjoint_step without the workspace: U* and mu in the library's
+        fixed device scratch (grids up to 1024^2 cells in FP64, 2 x 1024^2
+        in FP32); allocates nothing.  Calls on one GPU must not overlap."""
+        import torch
+        with torch.cuda.device(self.device):  # the stream's device must be current
+            _check(lib().lf_adjoint_step_noalloc(self._ctx, self._arg(Un, "Un"), float(dt),
+                                                 self._arg(lam_np1, "lam_np1"), self._arg(lam_n, "lam_n"),
+                                                 self._stream()), "lf_adjoint_step_noalloc")
 
     def totals(self, U) -> np.ndarray:
         out = (ctypes.c_double * self.shape[0])()

@@ -8,6 +8,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "lagrangeflux.h"
@@ -57,6 +58,38 @@ void* mu_of(const lf_ctx* c, void* ws) { return static_cast<char*>(ws) + c->L.mu
 
 constexpr size_t kCtlHeader = offsetof(lf::Ctl, dt_hist);
 
+// ---- scratch of lf_adjoint_step_noalloc ------------------------------------
+//
+// The predictor state U* and the adjoint intermediate mu of that entry point
+// live in this array instead of a caller workspace.  Every GPU the library
+// runs on holds its own copy from the module's load until the process ends.
+// In host code the name stands for a host-side handle, not a device
+// address: its address on a device comes from hipGetSymbolAddress (with
+// that device current), once per device, and only that address is passed
+// to kernels.
+constexpr size_t kNoAllocScratch = LF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of scratch, per device
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Device address of scratch on device dev (resolved on first use, with dev
+// current).
+int scratch_on(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return LF_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LF_ERR_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return LF_OK;
+}
+
 int read_ctl(lf::Ctl* dev, lf::Ctl* host, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(host, dev, kCtlHeader, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return LF_ERR_HIP;
@@ -91,6 +124,7 @@ const char* lf_status_string(int status) {
     case LF_ERR_HIP: return "HIP runtime error";
     case LF_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
     case LF_ERR_STATE: return "invalid context state";
+    case LF_ERR_TOO_LARGE: return "grid too large for the no-allocation scratch (LF_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }
@@ -290,6 +324,38 @@ int lf_adjoint_step_ustar(lf_ctx* ctx, const void* Un, const void* Ustar, double
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* mu = mu_of(ctx, ws);
   hipError_t e = lf::launch_adjoint(ctx->g, lf::kAdjCorr, Ustar, lam_np1, nullptr, mu, dt, s);
+  if (e == hipSuccess) e = lf::launch_adjoint(ctx->g, lf::kAdjPred, Un, mu, lam_np1, lam_n, dt, s);
+  return hip_status(e);
+}
+
+int lf_adjoint_step_noalloc(lf_ctx* ctx, const void* Un, double dt, const void* lam_np1, void* lam_n,
+                            void* stream) {
+  if (!ctx || !Un || !lam_np1 || !lam_n || ctx->g.ns != 0 || ctx->g.recon != 0) return LF_ERR_ARG;
+  if (!(dt >= 0.0) || !isfinite(dt)) return LF_ERR_ARG;
+  const size_t n = ctx->state_bytes;
+  if (overlap(lam_n, n, Un, n) || overlap(lam_n, n, lam_np1, n)) return LF_ERR_ARG;
+  // U* and mu, each 256-byte aligned, must fit the scratch
+  const size_t half = align256(n);
+  if (2 * half > kNoAllocScratch) return LF_ERR_TOO_LARGE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the scratch of the device the stream belongs to, which must be the
+  // current device (the address is resolved with it current)
+  int cur = 0;
+  hipDevice_t sdev = 0;
+  if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice(s, &sdev) != hipSuccess) return LF_ERR_HIP;
+  if (sdev != cur) return LF_ERR_ARG;
+  void* base = nullptr;
+  const int rc = scratch_on(cur, &base);
+  if (rc != LF_OK) return rc;
+  if (overlap(Un, n, base, kNoAllocScratch) || overlap(lam_np1, n, base, kNoAllocScratch) ||
+      overlap(lam_n, n, base, kNoAllocScratch))
+    return LF_ERR_ARG;
+  void* us = base;
+  void* mu = static_cast<char*>(base) + half;
+  // U* and mu are written in full before they are read: nothing in the
+  // scratch needs clearing between calls
+  hipError_t e = lf::launch_stage(ctx->g, lf::kPredictor, Un, nullptr, us, dt, nullptr, false, false, s);
+  if (e == hipSuccess) e = lf::launch_adjoint(ctx->g, lf::kAdjCorr, us, lam_np1, nullptr, mu, dt, s);
   if (e == hipSuccess) e = lf::launch_adjoint(ctx->g, lf::kAdjPred, Un, mu, lam_np1, lam_n, dt, s);
   return hip_status(e);
 }

@@ -164,6 +164,36 @@ def test_conservative_reconstruction_context_validation():
     lib.lf_destroy(ctx)
 
 
+def test_noalloc_entry_validates_before_hip():
+    """lf_adjoint_step_noalloc refuses a grid whose U* and mu do not fit
+    its fixed scratch (LF_ERR_TOO_LARGE: FP64 beyond 1024^2 cells, FP32
+    beyond 2 x 1024^2) and bad arguments (LF_ERR_ARG), before any HIP
+    call."""
+    import paper_1607_08710_amd as L
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    A, B, C = vp(0x1000000), vp(0x40000000), vp(0x80000000)
+    for dtype, nx, ny in ((L.LF_F64, 1025, 1024), (L.LF_F64, 1024, 1025), (L.LF_F32, 2049, 1024),
+                          (L.LF_F32, 2048, 1025)):
+        ctx, _ = L.init(_params(nx=nx, ny=ny, dtype=dtype))
+        assert lib.lf_adjoint_step_noalloc(ctx, A, 0.1, B, C, None) == L.LF_ERR_TOO_LARGE
+        lib.lf_destroy(ctx)
+    assert L.status_string(L.LF_ERR_TOO_LARGE).startswith("grid too large")
+    ctx, _ = L.init(_params(nx=1024, ny=1024))
+    E = L.LF_ERR_ARG
+    assert lib.lf_adjoint_step_noalloc(None, A, 0.1, B, C, None) == E
+    assert lib.lf_adjoint_step_noalloc(ctx, None, 0.1, B, C, None) == E
+    assert lib.lf_adjoint_step_noalloc(ctx, A, -0.1, B, C, None) == E
+    assert lib.lf_adjoint_step_noalloc(ctx, A, float("nan"), B, C, None) == E
+    assert lib.lf_adjoint_step_noalloc(ctx, A, 0.1, B, B, None) == E   # lam_n is lam_np1
+    assert lib.lf_adjoint_step_noalloc(ctx, A, 0.1, B, A, None) == E   # lam_n is Un
+    lib.lf_destroy(ctx)
+    for kw in (dict(n_species=1), dict(reconstruction=L.LF_RECON_CONSERVATIVE)):
+        ctx, _ = L.init(_params(**kw))
+        assert lib.lf_adjoint_step_noalloc(ctx, A, 0.1, B, C, None) == E
+        lib.lf_destroy(ctx)
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     import paper_1607_08710_amd as L
