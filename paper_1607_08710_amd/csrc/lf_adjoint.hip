@@ -349,15 +349,17 @@ static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, con
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.dt = dt;
-  // strip height: 32 rows, halved (to 8) until ~16k waves exist (the best
-  // measured at 4096^2, 16 rows, and 8192^2, 32 rows, in both precisions);
-  // LF_ADJ_ROWS (a power of two, 4..4096) overrides it (launch shape only)
+  // strip height: 32 rows, halved (to 8) until about 8k waves (FP64) or
+  // 16k waves (FP32) exist: the best measured at 4096^2 (32 rows in FP64,
+  // 2% faster than 16; 16 rows in FP32, 2% faster than 32) and at 8192^2
+  // (32 rows); LF_ADJ_ROWS (4..4096) overrides it (launch shape only)
   const int tiles_x = (g.nx + kAdjTileW - 1) / kAdjTileW;
+  const long long min_waves = sizeof(T) == 8 ? 8192 : 16384;
   int r = 32;
-  while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < 16384) r /= 2;
+  while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < min_waves) r /= 2;
   if (const char* env = getenv("LF_ADJ_ROWS")) {
     const int v = atoi(env);
-    if (v >= 4 && v <= 4096 && (v & (v - 1)) == 0) r = v;
+    if (v >= 4 && v <= 4096) r = v;
   }
   if (r > g.ny) r = g.ny;
   a.rows = r;

@@ -220,26 +220,30 @@ __device__ __forceinline__ T sweby(T a, T b, T beta) {
 // Value of eq. (sweby) and half its partial derivatives in one pass (a
 // face value is w + phi/2 or w - phi/2, so the adjoint needs the partials
 // of phi/2), with the conventions: zero when ab <= 0; min(x, y) follows x
-// when x <= y; max(m1, m2) follows m1 when m1 >= m2.  (a and b share their
-// sign when ab > 0, so the sign factors cancel in the derivatives.)  The
-// limited value follows one of |a|, beta |b| (through m1) or beta |a|, |b|
-// (through m2): its partial is 1 or beta with respect to the argument it
-// follows and 0 with respect to the other; hbeta = beta / 2.  The value is
-// the max-min form itself; for beta >= 1 it equals sweby() bit for bit.
+// when x <= y; max(m1, m2) follows m1 when m1 >= m2, where m1 = min(|a|,
+// beta |b|) and m2 = min(beta |a|, |b|).  (a and b share their sign when
+// ab > 0, so the sign factors cancel in the derivatives.)  For beta >= 1
+// these select, with x = |a| and y = |b|:
+//   x < y:  min(beta x, y), following beta x (partials beta, 0) when
+//           beta x <= y, else y (0, 1);
+//   x >= y: min(x, beta y), following x (1, 0) when x <= beta y, else
+//           beta y (0, beta);
+// i.e. phi = min(p, q) with (p, q) = (beta x, y) or (x, beta y), following
+// a when p <= q, with the unit coefficient exactly when that choice differs
+// from x < y.  For beta = 0 the value and both partials are 0, as the
+// max-min form gives.  The value equals the max-min form, and sweby(), bit
+// for bit (min and max return one of their exact arguments); hbeta =
+// beta / 2.
 template <typename T>
 __device__ __forceinline__ void sweby_all(T a, T b, T beta, T hbeta, T& phi, T& hda, T& hdb) {
-  const T aa = fabs(a), ab = fabs(b);
-  const T ba = beta * aa, bb = beta * ab;
-  const T m1 = fmin(aa, bb);   // min(|a|, beta |b|)
-  const T m2 = fmin(ba, ab);   // min(beta |a|, |b|)
+  const T x = fabs(a), y = fabs(b);
+  const bool lt = x < y;
+  const T p = lt ? beta * x : x;
+  const T q = lt ? y : beta * y;
   const bool act = a * b > T(0);
-  const bool m1a = aa <= bb;   // m1 follows |a|
-  const bool m2a = ba <= ab;   // m2 follows beta |a|
-  const bool first = m1 >= m2; // max follows m1
-  phi = act ? copysign(fmax(m1, m2), a) : T(0);
-  const bool fa = first ? m1a : m2a;      // follows a
-  const bool unit = first ? m1a : !m2a;   // follows |a| or |b|, unscaled
-  const T hc = unit ? T(0.5) : hbeta;
+  const bool fa = p <= q;                       // follows a
+  phi = act ? copysign(fmin(p, q), a) : T(0);
+  const T hc = (fa != lt) ? T(0.5) : hbeta;     // coefficient 1 or beta, halved
   hda = (act && fa) ? hc : T(0);
   hdb = (act && !fa) ? hc : T(0);
 }

@@ -180,3 +180,59 @@ def test_limiter_variant_four_quadrant_f64(beta):
     T = np.ascontiguousarray(np.transpose(Ug, (0, 2, 1)))
     T[[1, 2]] = T[[2, 1]]
     assert np.array_equal(T, Ug)
+
+
+# ---- the adjoint at the limiter's ties --------------------------------------------
+
+# Differences (in units of 1/64) that put the limiter on each of its ties
+# for beta = 1, 1.5 and 2: |a| = |b|, beta |a| = |b|, |a| = beta |b|, a sign
+# change and a zero difference.
+TIE_STEPS = {1.0: [2, 2, 3, 2, 2, 3, 3, -2, 0, 2, 4, 2],
+             1.5: [2, 2, 3, 2, 2, 3, 3, -2, 0, 2, 4, 2],
+             2.0: [2, 2, 4, 2, 2, 4, 4, -2, 0, 2, 3, 2]}
+
+
+def _tie_profile(n, beta, shift):
+    d = np.array(TIE_STEPS[beta], dtype=np.float64) / 64.0
+    return np.concatenate([[0.0], np.cumsum(np.resize(np.roll(d, shift), n - 1))])
+
+
+@pytest.mark.parametrize("beta", [1.0, 1.5, 2.0])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
+@pytest.mark.parametrize("moving", [False, True])
+def test_residual_vjp_at_limiter_ties(beta, bc, moving):
+    """J_R(U)^T g where every primitive difference sits on a tie of the
+    limiter (exact dyadic values, gamma = 1.5): the one-sided derivatives
+    the adjoint takes there follow the conventions of eq. (sweby)'s max-min
+    form (min follows its first argument, max its first, zero when ab <=
+    0), on both sides; a different choice would change the result by O(1).
+    Moving: rho = 1, and u, v, p carry the ties.  At rest: rho carries them
+    and p = rho, so that c_L = c_R at every face as well (the sound speed's
+    tie, which follows the left side).  Both forms of the perfect-gas law
+    (the oracle's, through the specific energy, and the kernels') recover
+    the primitive variables bit for bit, or the ties would not survive."""
+    nx, ny = 70, 45
+    cx = lambda s: _tie_profile(nx, beta, s)[None, :]
+    cy = lambda s: _tie_profile(ny, beta, s)[:, None]
+    if moving:
+        rho = np.ones((ny, nx))
+        u = 0.25 + cx(1) - cy(5)
+        v = -0.25 + cx(7) + cy(2)
+        p = 1.0 + cx(3) + cy(9)
+    else:
+        rho = 1.0 + cx(0) + cy(4)
+        u = np.zeros((ny, nx))
+        v = np.zeros((ny, nx))
+        p = rho.copy()
+    U = workloads.prim_to_cons(1.5, rho, u, v, p)
+    w = np.array([oracle.cons_to_prim(1.5, U[:, j, i]) for j in range(ny) for i in range(nx)])
+    assert np.array_equal(w, np.stack([rho, u, v, p], axis=-1).reshape(-1, 4))
+    assert np.array_equal(0.5 * (U[3] - 0.5 * (U[1] * u + U[2] * v)), p)  # the kernels' form
+    cfg = dict(nx=nx, ny=ny, dx=1.0 / nx, dy=1.0 / nx, gamma=1.5, cfl=0.5, beta=beta, bc_x=bc[0], bc_y=bc[1])
+    g = np.random.default_rng(int(10 * beta) + bc[0]).standard_normal(U.shape)
+    S = solver_for(cfg)
+    out = S.empty_state()
+    S.residual_vjp(to_dev(U), to_dev(g), out)
+    ref = oracle.residual_vjp(oracle_params(cfg), U, g)
+    err = rel_linf(to_host(out), ref)
+    assert np.all(err <= 1e-11), err

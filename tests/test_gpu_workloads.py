@@ -242,7 +242,7 @@ def test_adjoint_f32_gradient_decomposed_1024():
       * adjoint arithmetic: the FP32 gradient (rollout) against the FP64
         adjoint carried along the same FP32 trajectory (its states and U*
         upcast exactly, FP64 lf_adjoint_step_ustar, which the oracle pins):
-        measured 2.5e-7 relative L2; bar 2e-6, the size of FP32 rounding
+        measured 4.1e-7 relative L2; bar 2e-6, the size of FP32 rounding
         (1.2e-7) accumulated over 200 steps as a random walk (x sqrt(200));
       * trajectory: the FP32 gradient's distance from the FP64 gradient
         (measured 1.670e-3) is the distance of the FP64 adjoint along the
@@ -289,8 +289,8 @@ def test_adjoint_fd_1024_f32():
     """FP32 gradient against central differences of the FP32 forward map
     (200 steps at the frozen dt0, checkpoints every 20) along the 8 seeded
     directions.  The FP32 state's rounding and the limiter kinks set the
-    step size: measured over eps = 1e-2 .. 1e-4, eps = 1e-3 gives 3.8e-6 ..
-    1.9e-4 relative on the 8 directions (against the FP64 gradient the same
+    step size: measured over eps = 1e-2 .. 1e-4, eps = 1e-3 gives 1.2e-6 ..
+    1.8e-4 relative on the 8 directions (against the FP64 gradient the same
     differences give 3.8e-6 .. 1.9e-4).  Bar: 5e-4 at eps = 1e-3."""
     n = 1024
     U0, rho_tgt, cfg = workloads.adjoint_case(n)

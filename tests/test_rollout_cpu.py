@@ -57,6 +57,13 @@ def test_gradient_and_output_gradient_untouched(steps, ckpt):
     assert g.data_ptr() != v.data_ptr()
     assert torch.allclose(g, v_before * A ** steps, rtol=1e-14, atol=0)
     assert S.calls["adjoint"] == steps
+    # every step runs once forward; the backward pass recomputes all but the
+    # last segment (kept by the forward pass), whose last step needs only
+    # its predictor stage
+    nseg = (steps + ckpt - 1) // ckpt
+    tail = steps - (nseg - 1) * ckpt
+    assert S.calls["step"] + S.calls["step_save"] == steps + (steps - tail) - (nseg - 1)
+    assert S.calls["stage"] == nseg - 1
 
 
 def test_empty_rollout():
