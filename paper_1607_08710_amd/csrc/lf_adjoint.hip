@@ -168,11 +168,13 @@ void adjoint_kernel(AdjArgs<T> a) {
   // rows are addressed as a uniform row pointer (scalar registers) plus
   // the lane's byte offset (see ld_lane)
   const unsigned boff = unsigned(cm) * sizeof(T);
-  auto load_u = [&](int row) -> P4<T> {
+  // raw conservative values of U at (row, this lane's column)
+  auto load_q = [&](int row) -> P4<T> {
     const T* rp = a.U + (long long)map_index<BCY>(row, ny) * nx;
     const unsigned bo = lane_offset(rp, boff);
-    return prim4(ld_lane(rp, bo), ld_lane(rp + P, bo), ld_lane(rp + 2 * P, bo), ld_lane(rp + 3 * P, bo), gm1);
+    return {ld_lane(rp, bo), ld_lane(rp + P, bo), ld_lane(rp + 2 * P, bo), ld_lane(rp + 3 * P, bo)};
   };
+  auto prim_of = [&](const P4<T>& q) { return prim4(q.r, q.u, q.v, q.p, gm1); };
   // cotangent of R at (row, this lane's column): zero outside a
   // transmissive domain (those cells do not exist)
   auto load_g = [&](int row) -> P4<T> {
@@ -183,15 +185,18 @@ void adjoint_kernel(AdjArgs<T> a) {
     return p4_sel(in, g);
   };
 
-
-  // window: prim rows k-2 .. k+1, g row k-1, y-accumulators rows k-2 ..
-  // k+1 (slots rotate every row).  g of the finished row is read again
-  // (from cache).  The slope data of row k (value and half partials) are
-  // handed to the next iteration, where they are row k-1's, through a
-  // per-wave LDS slot: each lane reads back its own values, so no barrier
-  // is needed; they are stored as soon as they are formed, so that they
-  // occupy no registers across the rest of the iteration.
+  // window: prim rows k-2 .. k+1, y-accumulators rows k-2 .. k+1 (slots
+  // rotate every row).  The rows of U and g an iteration uses were loaded
+  // one iteration earlier, so that their memory latency overlaps a whole
+  // row of arithmetic.  Per-wave LDS holds, for each lane, the slope data
+  // of row k (value and half partials; row k-1's in the next iteration)
+  // and the last three rows of g (rows k-2 .. k: the y-face and the x-faces
+  // of row k-2 read them back).  Each lane reads back its own values, so
+  // no barrier is needed; the slope data are stored as soon as they are
+  // formed, so that they occupy no registers across the rest of the
+  // iteration.
   __shared__ T scarry[WPB][12][kWave];
+  __shared__ T gring[WPB][3][4][kWave];
   T(*my_c)[kWave] = scarry[w];
   auto put_slope = [&](const SlopeD<T>& S) {
     const T v[12] = {S.s.r, S.s.u, S.s.v, S.s.p, S.hda.r, S.hda.u, S.hda.v, S.hda.p,
@@ -199,7 +204,7 @@ void adjoint_kernel(AdjArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < 12; ++i) my_c[i][lane] = v[i];
   };
-  // read through a volatile LDS pointer: otherwise the compiler forwards
+  // read through volatile LDS pointers: otherwise the compiler forwards
   // the stored values and keeps them in registers across the iteration
   using LdsV = __attribute__((address_space(3))) volatile T;
   LdsV* my_v = (LdsV*)&scarry[w][0][lane];
@@ -210,20 +215,40 @@ void adjoint_kernel(AdjArgs<T> a) {
     S.hdb = {my_v[8 * kWave], my_v[9 * kWave], my_v[10 * kWave], my_v[11 * kWave]};
     return S;
   };
-  P4<T> Wm2 = load_u(y0 - 3), Wm1 = load_u(y0 - 2), W0 = load_u(y0 - 1);
+  auto gslot = [](int row) { return (row % 3 + 3) % 3; };
+  auto put_g = [&](int row, const P4<T>& g) {
+    T(*sl)[kWave] = gring[w][gslot(row)];
+    sl[0][lane] = g.r;
+    sl[1][lane] = g.u;
+    sl[2][lane] = g.v;
+    sl[3][lane] = g.p;
+  };
+  auto get_g = [&](int row) -> P4<T> {
+    LdsV* gv = (LdsV*)&gring[w][gslot(row)][0][lane];
+    return {gv[0], gv[kWave], gv[2 * kWave], gv[3 * kWave]};
+  };
+  P4<T> Wm2 = prim_of(load_q(y0 - 3)), Wm1 = prim_of(load_q(y0 - 2)), W0 = prim_of(load_q(y0 - 1));
   // slope data of row y0-2 (rows y0-3 .. y0-1)
   put_slope(slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
                     {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta, hbeta));
-  P4<T> Gm1 = load_g(y0 - 2);
+  put_g(y0 - 2, load_g(y0 - 2));
+  // in flight: U row k+1 and g row k of the first iteration
+  P4<T> Qn = load_q(y0), Gn = load_g(y0 - 1);
   const P4<T> Z = {T(0), T(0), T(0), T(0)};
   P4<T> Am2 = Z, Am1 = Z, A0 = Z;  // accumulators for rows k-2, k-1, k
   P4<T> ghost_lo = Z;              // transmissive: slots aimed at rows < 0
 
 #pragma unroll 1
   for (int k = y0 - 1; k <= y1 + 1; ++k) {
-    // new data: prim row k+1, g row k
-    const P4<T> W1 = load_u(k + 1);
-    const P4<T> Gk = load_g(k);
+    // new data: prim row k+1, g row k (loaded last iteration); then the
+    // loads for the next iteration (rows past the strip are mapped like
+    // any other row and simply not used)
+    const P4<T> W1 = prim_of(Qn);
+    const P4<T> Gk = Gn;
+    const P4<T> Gm1 = get_g(k - 1);
+    put_g(k, Gk);
+    Qn = load_q(k + 2);
+    Gn = load_g(k + 1);
     // slopes of rows k-1 (rows k-2, k-1, k; carried) and k (rows k-1, k,
     // k+1)
     const SlopeD<T> Sk1 = get_slope();
@@ -254,7 +279,7 @@ void adjoint_kernel(AdjArgs<T> a) {
         if (r == ny - 1) tot = p4_add(tot, p4_add(Am1, A0));  // rows ny, ny+1 are ghosts
       }
       // x-faces of row r across the lanes (Wm2 = prim row r)
-      const P4<T> Gm2 = load_g(r);
+      const P4<T> Gm2 = get_g(r);
       const P4<T> wr1 = p4_shl(Wm2);
       const P4<T> dxp = {wr1.r - Wm2.r, wr1.u - Wm2.u, wr1.v - Wm2.v, wr1.p - Wm2.p};
       const P4<T> dxm = p4_shr(dxp);
@@ -322,7 +347,6 @@ void adjoint_kernel(AdjArgs<T> a) {
     Wm2 = Wm1;
     Wm1 = W0;
     W0 = W1;
-    Gm1 = Gk;
     Am2 = Am1;
     Am1 = A0;
     A0 = A1;
