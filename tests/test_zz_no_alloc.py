@@ -4,7 +4,10 @@ against lf_adjoint_step with a caller workspace: bit for bit, on calls in a
 row on one GPU, each followed by one on a smaller grid (the scratch then
 still holds the larger grid's data), in both precisions; the first case of
 each precision is the largest grid the scratch admits.  Calls after the
-first on the device allocate no device memory."""
+first on the device allocate no device memory.  And it runs inside a
+captured HIP graph (the callers it is for): replays with eager work and
+synchronisations between them, and the inputs changed in place, each
+equal to lf_adjoint_step run eagerly on the same inputs."""
 import numpy as np
 import pytest
 
@@ -63,3 +66,35 @@ def test_noalloc_refuses_oversize_grid():
     with pytest.raises(L.LFError) as e:
         S.adjoint_step_noalloc(U, 1e-3, lam, out)
     assert e.value.status == L.LF_ERR_TOO_LARGE
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_noalloc_adjoint_step_in_a_graph(dtype):
+    import torch
+    nx, ny = 257, 190
+    cfg = dict(nx=nx, ny=ny, dx=1.0 / nx, dy=1.0 / nx, gamma=1.4, cfl=0.5, beta=1.5, bc_x=0, bc_y=1)
+    S = solver_for(cfg, dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    U = torch.from_numpy(workloads.random_state(nx, ny, seed=41)).to(device="cuda", dtype=tdt)
+    lam = torch.from_numpy(np.random.default_rng(42).standard_normal((4, ny, nx))).to(device="cuda", dtype=tdt)
+    dt = S.dt(U)
+    out = S.empty_state()
+    S.adjoint_step_noalloc(U, dt, lam, out)  # first call on the device: outside capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        S.adjoint_step_noalloc(U, dt, lam, out)
+    ref = S.empty_state()
+    for rep in range(4):
+        if rep:
+            # change the inputs in place (the graph reads them where they are)
+            U.mul_(1.0 + 1e-3 * rep)
+            lam.copy_(torch.roll(lam, shifts=rep, dims=2))
+        out.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda", dtype=tdt).sum()  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        S.adjoint_step(U, dt, lam, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        assert bool(torch.isfinite(junk))
