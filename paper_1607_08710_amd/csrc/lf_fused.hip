@@ -284,7 +284,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     load_row(plo, q0);
     load_row(plo + 1, q1);
     load_row(plo + 2, QA);
-    if (plo + 3 <= nlast) load_row(plo + 3, QB);
+    load_row(min(plo + 3, nlast), QB);
     put_n(plo, q0);
     put_n(plo + 1, q1);
     PW = prime_window<CONS, NS>(row_vars<CONS, NS>(qa, gm1), row_vars<CONS, NS>(qb, gm1),
@@ -303,7 +303,10 @@ void fused_step_kernel(FusedArgs<T> a) {
     put_n(pr + 2, QA);
 #pragma unroll
     for (int f = 0; f < NF; ++f) QA[f] = QB[f];
-    if (pr + 4 <= nlast) load_row(pr + 4, QB);
+    // unconditional (past the last row it re-reads that row, unused), so
+    // that the compiler can count the loads in flight and wait only for the
+    // row it needs, not for the one loaded a row later
+    load_row(min(pr + 4, nlast), QB);
     T bal[NF];  // flux balances
     window_row<CONS, NS>(PW, rn, beta, h, gam, gm1, igm1, kxy, bal);
     const int sn = nslot(pr);
