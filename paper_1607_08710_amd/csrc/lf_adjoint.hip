@@ -57,6 +57,45 @@ struct P4 {
   T r, u, v, p;
 };
 
+// ---- rows as buffer resources ---------------------------------------------
+//
+// One row of one field plane is a buffer resource: its base address and its
+// length in bytes sit in scalar registers, and each lane adds its own byte
+// offset, a loop-invariant vector register.  The hardware drops a store
+// whose offset lies past the length (and a load there returns zero), so a
+// lane that must not store gets an offset past the row instead of a branch
+// around the store: the loop then has no path without stores, and the
+// compiler can count the memory operations in flight exactly.
+constexpr unsigned kOffNone = 0x80000000u;  // past any row: access dropped
+// descriptor word 3 of a raw (untyped) gfx9 buffer: 32-bit data format
+constexpr int kRawBufferWord3 = 0x00020000;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T* row, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(row), 0, n * int(sizeof(T)), kRawBufferWord3);
+}
+typedef unsigned int U32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double buf_ld(double*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_ld(float*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ T ld_row(const T* row, int n, unsigned off) {
+  return buf_ld((T*)nullptr, row_rsrc(row, n), off);
+}
+template <typename T>
+__device__ __forceinline__ void st_row(T* row, int n, unsigned off, T v) {
+  buf_st(row_rsrc(row, n), off, v);
+}
+
 template <typename T>
 __device__ __forceinline__ P4<T> p4_shl(const P4<T>& a) {
   return {shl1(a.r), shl1(a.u), shl1(a.v), shl1(a.p)};
@@ -151,7 +190,9 @@ void adjoint_kernel(AdjArgs<T> a) {
   if (lb_ >= a.blocks) return;  // whole block
   const int by = lb_ / a.blocks_x;
   const int bx = lb_ - by * a.blocks_x;
-  const int w = threadIdx.x >> 6;
+  // wave-uniform, and known to be (LDS bases derived from it can go to
+  // scalar registers)
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = a.nx, ny = a.ny;
   const int c = (bx * WPB + w) * kAdjTileW - kAdjHalo + lane;  // unwrapped column of this lane
@@ -165,14 +206,15 @@ void adjoint_kernel(AdjArgs<T> a) {
   const long long P = a.plane;
   const T gm1 = a.gm1, gam = a.gamma, igm1 = a.inv_gm1, beta = a.beta, hbeta = a.hbeta;
 
-  // rows are addressed as a uniform row pointer (scalar registers) plus
-  // the lane's byte offset (see ld_lane)
+  // rows are buffer resources (see row_rsrc) addressed with the lane's byte
+  // offset; output lanes hold columns 0 .. nx-1, where cm = c
   const unsigned boff = unsigned(cm) * sizeof(T);
+  const unsigned soff = out_lane ? boff : kOffNone;
   // raw conservative values of U at (row, this lane's column)
   auto load_q = [&](int row) -> P4<T> {
     const T* rp = a.U + (long long)map_index<BCY>(row, ny) * nx;
-    const unsigned bo = lane_offset(rp, boff);
-    return {ld_lane(rp, bo), ld_lane(rp + P, bo), ld_lane(rp + 2 * P, bo), ld_lane(rp + 3 * P, bo)};
+    return {ld_row(rp, nx, boff), ld_row(rp + P, nx, boff), ld_row(rp + 2 * P, nx, boff),
+            ld_row(rp + 3 * P, nx, boff)};
   };
   auto prim_of = [&](const P4<T>& q) { return prim4(q.r, q.u, q.v, q.p, gm1); };
   // cotangent of R at (row, this lane's column): zero outside a
@@ -180,8 +222,8 @@ void adjoint_kernel(AdjArgs<T> a) {
   auto load_g = [&](int row) -> P4<T> {
     const bool in = (!YT || (row >= 0 && row < ny)) && (!XT || c_in);
     const T* rp = a.g + (long long)map_index<BCY>(row, ny) * nx;
-    const unsigned bo = lane_offset(rp, boff);
-    P4<T> g = {ld_lane(rp, bo), ld_lane(rp + P, bo), ld_lane(rp + 2 * P, bo), ld_lane(rp + 3 * P, bo)};
+    P4<T> g = {ld_row(rp, nx, boff), ld_row(rp + P, nx, boff), ld_row(rp + 2 * P, nx, boff),
+               ld_row(rp + 3 * P, nx, boff)};
     return p4_sel(in, g);
   };
 
@@ -227,13 +269,57 @@ void adjoint_kernel(AdjArgs<T> a) {
     LdsV* gv = (LdsV*)&gring[w][gslot(row)][0][lane];
     return {gv[0], gv[kWave], gv[2 * kWave], gv[3 * kWave]};
   };
+  // mode kAdjPred: lambda of the row an iteration outputs is copied from
+  // memory straight into LDS at the top of the iteration (buffer loads with
+  // the LDS flag: lane l's 32-bit word lands at M0 + 4 l), so that its
+  // latency overlaps the iteration's arithmetic without holding registers.
+  // All lanes copy their column (cm, in range); the halo lanes' values go
+  // unused.  The compiler does not track these LDS writes: the reads wait
+  // for them explicitly (lam_wait).
+  constexpr int kDw = int(sizeof(T) / 4);  // 32-bit words per value
+  __shared__ unsigned lam_lds[WPB][MODE == kAdjPred ? 4 : 1][kDw][kWave];
+  auto fetch_lam = [&](int row) {
+    if constexpr (MODE == kAdjPred) {
+      const T* rp = a.lam + (long long)map_index<BCY>(row, ny) * nx;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(rp + f * P, nx);
+#pragma unroll
+        for (int h = 0; h < kDw; ++h)  // word h of the value: scalar offset 4 h
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (__attribute__((address_space(3))) void*)&lam_lds[w][f][h][0], 4, boff, 4 * h, 0, 0);
+      }
+    }
+  };
+  // every memory load of this wave complete: the copies above included
+  auto lam_wait = [] { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); };
+  auto lam_at = [&](int f) -> T {
+    if constexpr (sizeof(T) == 8) {
+      const unsigned long long lo = lam_lds[w][f][0][lane], hi = lam_lds[w][f][kDw - 1][lane];
+      return __builtin_bit_cast(T, (hi << 32) | lo);
+    } else {
+      return __builtin_bit_cast(T, lam_lds[w][f][0][lane]);
+    }
+  };
   P4<T> Wm2 = prim_of(load_q(y0 - 3)), Wm1 = prim_of(load_q(y0 - 2)), W0 = prim_of(load_q(y0 - 1));
   // slope data of row y0-2 (rows y0-3 .. y0-1)
   put_slope(slope_d({Wm1.r - Wm2.r, Wm1.u - Wm2.u, Wm1.v - Wm2.v, Wm1.p - Wm2.p},
                     {W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p}, beta, hbeta));
   put_g(y0 - 2, load_g(y0 - 2));
-  // in flight: U row k+1 and g row k of the first iteration
-  P4<T> Qn = load_q(y0), Gn = load_g(y0 - 1);
+  // In flight when the loop starts: U row k+1 and g row k of the first
+  // iteration, then four stores that write nothing (an empty range).  The
+  // loop is thus entered with the same memory operations in flight, in the
+  // same order, as it goes round with (a U row, a g row, a row's four
+  // stores).  The compiler counts the operations in flight over both ways
+  // into the loop and keeps the smaller count, so any difference here would
+  // make the loop's waits for its loads also wait for the stores of the
+  // row before (a drain of every access in flight at the top of each row).
+  P4<T> Qn = load_q(y0);
+  __builtin_amdgcn_sched_barrier(0);
+  P4<T> Gn = load_g(y0 - 1);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) st_row(a.out + f * P, 0, soff, T(0));  // four distinct stores
   const P4<T> Z = {T(0), T(0), T(0), T(0)};
   P4<T> Am2 = Z, Am1 = Z, A0 = Z;  // accumulators for rows k-2, k-1, k
   P4<T> ghost_lo = Z;              // transmissive: slots aimed at rows < 0
@@ -242,16 +328,20 @@ void adjoint_kernel(AdjArgs<T> a) {
   for (int k = y0 - 1; k <= y1 + 1; ++k) {
     // new data: prim row k+1, g row k (loaded last iteration); then the
     // loads for the next iteration (rows past the strip are mapped like
-    // any other row and simply not used)
+    // any other row and simply not used).  Everything this iteration reads
+    // from LDS is read here, at the top, so that the reads' latency
+    // overlaps the arithmetic.
+    const SlopeD<T> Sk1 = get_slope();
     const P4<T> W1 = prim_of(Qn);
     const P4<T> Gk = Gn;
     const P4<T> Gm1 = get_g(k - 1);
-    put_g(k, Gk);
+    const P4<T> Gm2 = get_g(k - 2);  // row r = k-2 (its x-faces, below)
+    fetch_lam(k - 2);
     Qn = load_q(k + 2);
+    put_g(k, Gk);
     Gn = load_g(k + 1);
     // slopes of rows k-1 (rows k-2, k-1, k; carried) and k (rows k-1, k,
     // k+1)
-    const SlopeD<T> Sk1 = get_slope();
     const SlopeD<T> Sk = slope_d({W0.r - Wm1.r, W0.u - Wm1.u, W0.v - Wm1.v, W0.p - Wm1.p},
                                  {W1.r - W0.r, W1.u - W0.u, W1.v - W0.v, W1.p - W0.p}, beta, hbeta);
     put_slope(Sk);
@@ -272,6 +362,9 @@ void adjoint_kernel(AdjArgs<T> a) {
     if constexpr (YT) {
       if (r < 0) ghost_lo = p4_add(ghost_lo, Am2);
     }
+    // results of row r; rows below the strip (the first three iterations)
+    // have none, and their stores below are dropped
+    T res[4] = {T(0), T(0), T(0), T(0)};
     if (r >= y0) {
       P4<T> tot = Am2;
       if constexpr (YT) {
@@ -279,7 +372,6 @@ void adjoint_kernel(AdjArgs<T> a) {
         if (r == ny - 1) tot = p4_add(tot, p4_add(Am1, A0));  // rows ny, ny+1 are ghosts
       }
       // x-faces of row r across the lanes (Wm2 = prim row r)
-      const P4<T> Gm2 = get_g(r);
       const P4<T> wr1 = p4_shl(Wm2);
       const P4<T> dxp = {wr1.r - Wm2.r, wr1.u - Wm2.u, wr1.v - Wm2.v, wr1.p - Wm2.p};
       const P4<T> dxm = p4_shr(dxp);
@@ -319,9 +411,7 @@ void adjoint_kernel(AdjArgs<T> a) {
       vv[2] = tot.v * ir - gm1 * v * tot.p;
       vv[3] = gm1 * tot.p;
       const T gg[4] = {Gm2.r, Gm2.u, Gm2.v, Gm2.p};
-      T res[4];
-      // output lanes hold columns 0 .. nx-1, where cm = c
-      const long long roff = (long long)r * nx;
+      if constexpr (MODE == kAdjPred) lam_wait();
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if constexpr (MODE == kVjp) {
@@ -329,19 +419,24 @@ void adjoint_kernel(AdjArgs<T> a) {
         } else if constexpr (MODE == kAdjCorr) {
           res[f] = T(0.5 * (double(gg[f]) - a.dt * double(vv[f])));  // mu = (lam - dt v)/2
         } else {
-          const T* lp = a.lam + roff + f * P;
-          const T lam = out_lane ? ld_lane(lp, lane_offset(lp, boff)) : T(0);  // lam/2 + mu - dt v
+          const T lam = lam_at(f);  // lam/2 + mu - dt v
           res[f] = T(0.5 * double(lam) + double(gg[f]) - a.dt * double(vv[f]));
         }
       }
-      // stored straight from the lanes: the kernel is bound by arithmetic,
-      // and without staging no block barrier ties its waves together
-      if (out_lane) {
-        T* op = a.out + roff;
-        const unsigned bo = lane_offset(op, boff);
+    }
+    {
+      // stored straight from the lanes (the kernel is bound by arithmetic,
+      // and without staging no block barrier ties its waves together).  The
+      // stores are issued in every iteration, outside the branch above, so
+      // that no path through the loop lacks them and the compiler's count
+      // of memory operations in flight never makes a load wait for them;
+      // the halo lanes' stores are dropped (soff), and so are all of them
+      // in the rows below the strip (an empty range)
+      const bool mine = r >= y0;
+      const long long roff = (long long)(mine ? r : y0) * nx;
+      const int len = mine ? nx : 0;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) st_lane(op + f * P, bo, res[f]);
-      }
+      for (int f = 0; f < 4; ++f) st_row(a.out + roff + f * P, len, soff, res[f]);
     }
     // slide the window
     Wm2 = Wm1;
@@ -373,12 +468,12 @@ static hipError_t launch_adj_t(const Grid& g, const void* U, const void* gv, con
   a.idx = T(1.0 / g.dx);
   a.idy = T(1.0 / g.dy);
   a.dt = dt;
-  // strip height: 32 rows, halved (to 8) until about 8k waves (FP64) or
-  // 16k waves (FP32) exist: the best measured at 4096^2 (32 rows in FP64,
-  // 2% faster than 16; 16 rows in FP32, 2% faster than 32) and at 8192^2
-  // (32 rows); LF_ADJ_ROWS (4..4096) overrides it (launch shape only)
+  // strip height: 32 rows, halved (to 8) until about 8k waves exist: the
+  // best measured at 4096^2 (32 rows: 2-5% faster than 16, 24 or 48 in
+  // both precisions) and at 8192^2; LF_ADJ_ROWS (4..4096) overrides it
+  // (launch shape only)
   const int tiles_x = (g.nx + kAdjTileW - 1) / kAdjTileW;
-  const long long min_waves = sizeof(T) == 8 ? 8192 : 16384;
+  const long long min_waves = 8192;
   int r = 32;
   while (r > 8 && (long long)tiles_x * ((g.ny + r - 1) / r) < min_waves) r /= 2;
   if (const char* env = getenv("LF_ADJ_ROWS")) {
