@@ -282,19 +282,20 @@ struct Flux {
 template <typename T>
 __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceState<T>& R,
                                              T gamma, T inv_gm1, bool& left_out) {
-  // a = max(c_L, c_R): the side with the larger p/rho (compared as
-  // p_L rho_R >= p_R rho_L, both densities positive) sets a^2 = gamma p/rho.
-  const bool lside = L.p * R.r >= R.p * L.r;
-  const T ps_ = lside ? L.p : R.p;
-  const T rs_ = lside ? L.r : R.r;
+  // a = max(c_L, c_R), a^2 = gamma max(p_L/rho_L, p_R/rho_R)
+  //   = gamma max(p_L rho_R, p_R rho_L) / (rho_L rho_R)   (densities > 0),
+  // with no select: one reciprocal q = 1/(rho_L rho_R S) gives both
+  // 1/S = rho_L rho_R q and 1/(rho_L rho_R) = S q.
+  const T pr = L.p * R.r, rp = L.r * R.p;  // p_L rho_R, rho_L p_R
+  const T rr = L.r * R.r;
   const T S = L.r + R.r;
-  const T q = rcp(rs_ * S);          // 1 / (rho_s S)
-  const T iS = rs_ * q;              // 1 / S
-  const T a2 = gamma * ps_ * (S * q);  // gamma p_s / rho_s
-  const T ia = rsq(a2);              // 1 / a
+  const T q = rcp(rr * S);
+  const T iS = rr * q;                       // 1 / S
+  const T a2 = gamma * fmax(pr, rp) * (S * q);  // gamma p_s / rho_s
+  const T ia = rsq(a2);                      // 1 / a
   const T a = a2 * ia;
   // eq. (13): p* = (rho_R p_L + rho_L p_R)/S - (rho_L rho_R / S) a (u_R - u_L)
-  const T ps = fma(-(L.r * R.r * iS) * a, R.un - L.un, fma(R.r, L.p, L.r * R.p) * iS);
+  const T ps = fma(-(rr * iS) * a, R.un - L.un, (pr + rp) * iS);
   // eq. (14): u* = (rho_L u_L + rho_R u_R)/S - (p_R - p_L)/(S a)
   const T us = fma(-(R.p - L.p), iS * ia, fma(L.r, L.un, R.r * R.un) * iS);
   // upwind on the sign of u*: left when u* > 0
@@ -323,7 +324,9 @@ __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceSt
 
 // Vector-Jacobian product of face_flux: given the flux cotangent Fb,
 // returns the cotangents of the two face states.  The forward values are
-// recomputed exactly as face_flux() forms them.  Conventions at the kinks:
+// recomputed as face_flux() forms them, except the sound speed: it is
+// formed from the selected side's (p, rho), since its cotangent goes to
+// that side (the same value up to rounding).  Conventions at the kinks:
 // max(c_L, c_R) follows L on ties (p_L rho_R >= p_R rho_L); the upwind side
 // is L iff u* > 0.  Every division goes through one reciprocal and one
 // reciprocal square root: with q = 1/(rho_s S), 1/S = rho_s q,
