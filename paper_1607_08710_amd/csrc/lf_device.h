@@ -282,22 +282,38 @@ struct Flux {
 template <typename T>
 __device__ __forceinline__ Flux<T> face_flux(const FaceState<T>& L, const FaceState<T>& R,
                                              T gamma, T inv_gm1, bool& left_out) {
-  // a = max(c_L, c_R), a^2 = gamma max(p_L/rho_L, p_R/rho_R)
-  //   = gamma max(p_L rho_R, p_R rho_L) / (rho_L rho_R)   (densities > 0),
-  // with no select: one reciprocal q = 1/(rho_L rho_R S) gives both
-  // 1/S = rho_L rho_R q and 1/(rho_L rho_R) = S q.
+  // a = max(c_L, c_R), a^2 = gamma max(p_L/rho_L, p_R/rho_R), i.e.
+  // a^2 rho_L rho_R = gamma max(p_L rho_R, p_R rho_L) =: g (densities > 0),
+  // with no select.
   const T pr = L.p * R.r, rp = L.r * R.p;  // p_L rho_R, rho_L p_R
   const T rr = L.r * R.r;
   const T S = L.r + R.r;
-  const T q = rcp(rr * S);
-  const T iS = rr * q;                       // 1 / S
-  const T a2 = gamma * fmax(pr, rp) * (S * q);  // gamma p_s / rho_s
-  const T ia = rsq(a2);                      // 1 / a
-  const T a = a2 * ia;
+  const T g = gamma * fmax(pr, rp);
+  T a, iSa, iS;  // a, 1/(S a), 1/S
+  if constexpr (sizeof(T) == 8) {
+    // one reciprocal square root for everything (the refined FP64 one costs
+    // six instructions, a reciprocal four): t = 1/sqrt(g rho_L rho_R S^2) =
+    // 1/(a rho_L rho_R S) gives a = g t S, 1/(S a) = t rho_L rho_R and
+    // 1/S = a/(S a)
+    const T t = rsq(g * rr * (S * S));
+    a = g * t * S;
+    iSa = t * rr;
+    iS = iSa * a;
+  } else {
+    // one instruction each; q = 1/(rho_L rho_R S) gives 1/S = rho_L rho_R q
+    // and 1/(rho_L rho_R) = S q (no product of four state values: FP32
+    // range)
+    const T q = rcp(rr * S);
+    iS = rr * q;
+    const T a2 = g * (S * q);
+    const T ia = rsq(a2);
+    a = a2 * ia;
+    iSa = iS * ia;
+  }
   // eq. (13): p* = (rho_R p_L + rho_L p_R)/S - (rho_L rho_R / S) a (u_R - u_L)
   const T ps = fma(-(rr * iS) * a, R.un - L.un, (pr + rp) * iS);
   // eq. (14): u* = (rho_L u_L + rho_R u_R)/S - (p_R - p_L)/(S a)
-  const T us = fma(-(R.p - L.p), iS * ia, fma(L.r, L.un, R.r * R.un) * iS);
+  const T us = fma(-(R.p - L.p), iSa, fma(L.r, L.un, R.r * R.un) * iS);
   // upwind on the sign of u*: left when u* > 0
   const bool left = us > T(0);
   left_out = left;
