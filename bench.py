@@ -421,6 +421,34 @@ def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
         if not timed:
             del x, UN, J
     full = e0.elapsed_time(e1) / 1e3
+    g_ckpt = x.grad
+    del x, UN, J
+    torch.cuda.empty_cache()
+    # the same gradient with every state and U* of the run kept in HBM
+    # (ckpt_every = steps: no recompute), when they fit with a margin
+    state_bytes = U0.numel() * U0.element_size()
+    need = 2 * steps * state_bytes
+    resident = None
+    same = None
+    if torch.cuda.mem_get_info()[0] > 1.15 * need:
+        try:
+            for timed in (False, True):
+                x = U0.clone().requires_grad_(True)
+                torch.cuda.synchronize()
+                e0.record()
+                UN = rollout(x, S, [dt] * steps, ckpt_every=steps)
+                J = 0.5 * cfg["dx"] * cfg["dy"] * ((UN[0] - rho_t) ** 2).sum()
+                J.backward()
+                e1.record()
+                torch.cuda.synchronize()
+                if timed:
+                    resident = e0.elapsed_time(e1) / 1e3
+                    same = bool(torch.equal(x.grad, g_ckpt))
+                del x, UN, J
+        except torch.cuda.OutOfMemoryError:
+            log("resident full gradient: out of device memory, not measured")
+            resident = same = None
+        torch.cuda.empty_cache()
     esz = 8 if dtype_flag == L.LF_F64 else 4
     res = {
         "lf_adjoint_step_per_s": 1.0 / bare,
@@ -429,9 +457,14 @@ def adjoint_leg(L, W, n, dtype_flag, steps, ckpt, reps):
         "lf_adjoint_step_ustar_per_s": 1.0 / bare_us,
         "full_gradient_steps_per_s": steps / full,
         "full_gradient_s": full,
-        "grad_finite": bool(torch.isfinite(x.grad).all().item()),
+        "grad_finite": bool(torch.isfinite(g_ckpt).all().item()),
+        # every state and U* of the run resident (2 x steps states, GB):
+        # no recompute; the gradient equals the checkpointed one bit for bit
+        "full_gradient_resident_steps_per_s": steps / resident if resident else None,
+        "full_gradient_resident_GB": need / 1e9,
+        "full_gradient_resident_equal": same,
     }
-    del U0, S, lam, out, x, UN
+    del U0, S, lam, out, g_ckpt
     torch.cuda.empty_cache()
     return res
 
