@@ -271,7 +271,7 @@ class Solver:
         return np.array(out[:])
 
 
-from .rollout import LagrangeFluxRollout, rollout  # noqa: E402
+from .rollout import LagrangeFluxRollout, checkpoint_spacing, rollout  # noqa: E402
 
-__all__ = ["Params", "Solver", "LagrangeFluxRollout", "rollout", "LFError", "NonPhysicalState",
+__all__ = ["Params", "Solver", "LagrangeFluxRollout", "rollout", "checkpoint_spacing", "LFError", "NonPhysicalState",
            "PERIODIC", "TRANSMISSIVE", "LF_F64", "LF_F32", "lib", "init", "status_string"]

@@ -14,13 +14,40 @@ that U*).
 
 Peak device memory: the checkpoints plus one segment of states and of
 predictor states (the last segment's are held from the forward pass to
-the backward pass).
+the backward pass).  With ``ckpt_every`` at least the step count the whole
+run is one segment, kept from the forward pass: nothing is recomputed.
+``ckpt_every="auto"`` takes the largest spacing whose peak fits in the
+free device memory (``checkpoint_spacing``): on a GPU with room for every
+state and predictor state of the run, that is the whole run.
 """
 from __future__ import annotations
 
-from typing import Sequence
+import math
+from typing import Sequence, Union
 
 import torch
+
+
+def checkpoint_spacing(n_steps: int, state_bytes: int, free_bytes: int, margin: float = 0.85) -> int:
+    """Largest checkpoint spacing C whose peak memory fits in ``margin``
+    of ``free_bytes``.  With spacing C the rollout holds about n/C
+    checkpoints plus one segment of C states and C predictor states, n/C +
+    2C states in all; C = n (the whole run kept, no recompute) needs 2n + 1.
+    When not even the smallest peak fits, returns the spacing of the
+    smallest peak, sqrt(n/2)."""
+    n = int(n_steps)
+    if n <= 1:
+        return 1
+    m = math.floor(margin * free_bytes / state_bytes)  # states that fit
+    if m >= 2 * n + 1:
+        return n
+    disc = m * m - 8 * n
+    if disc < 0:
+        return max(1, round(math.sqrt(n / 2)))
+    c = math.floor((m + math.sqrt(disc)) / 4)  # largest root of 2C^2 - mC + n = 0
+    while c > 1 and math.ceil(n / c) + 2 * c > m:  # rounding of the root
+        c -= 1
+    return max(1, min(n, c))
 
 
 class LagrangeFluxRollout(torch.autograd.Function):
@@ -94,5 +121,15 @@ class LagrangeFluxRollout(torch.autograd.Function):
         return lam, None, None, None
 
 
-def rollout(U0: torch.Tensor, solver, dts: Sequence[float], ckpt_every: int = 20) -> torch.Tensor:
-    return LagrangeFluxRollout.apply(U0, solver, dts, ckpt_every)
+def rollout(U0: torch.Tensor, solver, dts: Sequence[float], ckpt_every: Union[int, str] = 20,
+            free_bytes: int = None) -> torch.Tensor:
+    """U_N of the steps at the given dts, differentiable in U0.  ckpt_every:
+    checkpoint spacing, or "auto" for the largest one that fits in
+    ``free_bytes`` (default: the free memory of U0's device)."""
+    if ckpt_every == "auto":
+        if free_bytes is None:
+            if U0.device.type != "cuda":
+                raise ValueError('ckpt_every="auto" needs free_bytes for a tensor off the GPU')
+            free_bytes = torch.cuda.mem_get_info(U0.device)[0]
+        ckpt_every = checkpoint_spacing(len(dts), U0.numel() * U0.element_size(), free_bytes)
+    return LagrangeFluxRollout.apply(U0, solver, dts, int(ckpt_every))

@@ -80,3 +80,38 @@ def test_empty_rollout():
     assert torch.equal(g, v_before) and torch.equal(v, v_before)
     assert g.data_ptr() != v.data_ptr()
     assert sum(S.calls.values()) == 0
+
+
+def test_checkpoint_spacing():
+    from paper_1607_08710_amd.rollout import checkpoint_spacing
+    sb = 1 << 20
+    # room for the whole run (2n + 1 states): no recompute
+    assert checkpoint_spacing(200, sb, int((401 + 1) * sb / 0.85)) == 200
+    # less room: the largest C with ceil(n/C) + 2C <= states that fit
+    for n, m in ((200, 100), (200, 60), (200, 41), (1000, 200), (7, 9)):
+        c = checkpoint_spacing(n, sb, int(m * sb / 0.85) + 1)
+        assert -(-n // c) + 2 * c <= m
+        assert c == n or -(-n // (c + 1)) + 2 * (c + 1) > m
+    # not even the smallest peak fits: the spacing of the smallest peak
+    assert checkpoint_spacing(200, sb, 10 * sb) == 10
+    assert checkpoint_spacing(1, sb, 0) == 1
+
+
+@pytest.mark.parametrize("steps", [5, 30])
+def test_auto_spacing_gradient(steps):
+    """ckpt_every="auto" gives the gradient of every fixed spacing, with the
+    whole run kept when it fits (no recompute: no stage or step_save call
+    in the backward pass) and checkpoints when it does not."""
+    shape = (4, 3, 5)
+    sb = 4 * 3 * 5 * 8
+    x = torch.rand(shape, dtype=torch.float64, generator=torch.Generator().manual_seed(steps)).requires_grad_(True)
+    v = torch.rand(shape, dtype=torch.float64, generator=torch.Generator().manual_seed(steps + 1))
+    ref = torch.autograd.grad(rollout(x, LinearSolver(shape), [1e-3] * steps, ckpt_every=3), x, grad_outputs=v)[0]
+    for free, resident in ((10**9, True), (12 * sb, False)):
+        S = LinearSolver(shape)
+        UN = rollout(x, S, [1e-3] * steps, ckpt_every="auto", free_bytes=free)
+        fwd = dict(S.calls)
+        (g,) = torch.autograd.grad(UN, x, grad_outputs=v)
+        assert torch.equal(g, ref)
+        recomputed = S.calls["step_save"] - fwd["step_save"] + S.calls["stage"] - fwd["stage"]
+        assert (recomputed == 0) == resident
