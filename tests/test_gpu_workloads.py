@@ -340,6 +340,29 @@ def test_adjoint_rollout_vs_oracle():
     assert J == pytest.approx(Jref, rel=1e-12)
 
 
+def test_rollout_auto_spacing_bitwise():
+    """ckpt_every="auto" (on a GPU the whole run fits: nothing recomputed)
+    and a tight memory budget (checkpoints) give the checkpointed
+    gradient of a fixed spacing bit for bit."""
+    import torch
+    from paper_1607_08710_amd import checkpoint_spacing, rollout
+    n, steps = 256, 30
+    U0, rho_tgt, cfg = workloads.adjoint_case(n)
+    S = solver_for(cfg)
+    dt = S.dt(to_dev(U0))
+    tgt = to_dev(rho_tgt[None])[0]
+    grads = []
+    state_bytes = U0.size * 8
+    for ckpt, free in ((7, None), ("auto", None), ("auto", 20 * state_bytes)):
+        x = to_dev(U0).requires_grad_(True)
+        UN = rollout(x, S, [dt] * steps, ckpt_every=ckpt, free_bytes=free)
+        _misfit(UN, tgt, cfg["dx"], cfg["dy"]).backward()
+        grads.append(x.grad)
+    assert checkpoint_spacing(steps, state_bytes, torch.cuda.mem_get_info()[0]) == steps
+    assert checkpoint_spacing(steps, state_bytes, 20 * state_bytes) < steps
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
+
+
 # ---- Kelvin-Helmholtz 16384^2 -----------------------------------------------
 
 def test_kh_16384_sampled_step_and_f32():
