@@ -236,10 +236,12 @@ __device__ __forceinline__ T sweby(T a, T b, T beta) {
 // beta / 2.
 template <typename T>
 __device__ __forceinline__ void sweby_all(T a, T b, T beta, T hbeta, T& phi, T& hda, T& hdb) {
-  const T x = fabs(a), y = fabs(b);
-  const bool lt = x < y;
-  const T p = lt ? beta * x : x;
-  const T q = lt ? y : beta * y;
+  const bool lt = fabs(a) < fabs(b);
+  // the selects take the signed values and the magnitudes follow (|beta a|
+  // = beta |a|): the absolute values then fold into the operand modifiers
+  // of the compare and the minimum instead of being formed separately
+  const T p = fabs(lt ? beta * a : a);
+  const T q = fabs(lt ? b : beta * b);
   const bool act = a * b > T(0);
   const bool fa = p <= q;                       // follows a
   phi = act ? copysign(fmin(p, q), a) : T(0);
@@ -409,9 +411,18 @@ __device__ __forceinline__ void face_flux_vjp(const FaceState<T>& L, const FaceS
   // the sound-speed and upwind terms each go to one side: the left
   // side's share is selected and the right side takes the rest, x - share,
   // which is exactly x or 0
-  const T darL = aleft ? dar : T(0), dapL = aleft ? dap : T(0);
-  const T rbL = left ? rb : T(0), unbL = left ? unb : T(0);
-  const T utbL = left ? utb : T(0), pbL = left ? pb : T(0);
+  T darL, dapL, rbL, unbL, utbL, pbL;
+  if constexpr (sizeof(T) == 8) {
+    // weights 1 or 0 (one select each, the low word being zero) instead of
+    // a select per double: x w is x or a zero
+    const T wa = aleft ? T(1) : T(0), wl = left ? T(1) : T(0);
+    darL = dar * wa, dapL = dap * wa;
+    rbL = rb * wl, unbL = unb * wl, utbL = utb * wl, pbL = pb * wl;
+  } else {
+    darL = aleft ? dar : T(0), dapL = aleft ? dap : T(0);
+    rbL = left ? rb : T(0), unbL = left ? unb : T(0);
+    utbL = left ? utb : T(0), pbL = left ? pb : T(0);
+  }
   Lb.r = rlb + darL + rbL;
   Lb.un = unlb + unbL;
   Lb.ut = utbL;
