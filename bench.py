@@ -755,6 +755,9 @@ def main():
         hbm_roofline = {"definition": "cell-updates/s x bytes per cell-step of the two-pass design "
                                       "(predictor R 32 + W 32, corrector R 64 + W 32 in FP64; half in FP32) / "
                                       "8 TB/s",
+                        "note": "the single pass keeps U* on chip and moves 64 (FP64) / 32 (FP32) of those "
+                                "bytes per cell-step, so its fraction can exceed 1; the two-stage path "
+                                "moves them all",
                         "peak_GBps": HBM_PEAK_GBPS}
         for name, r, esz in (("f64", f64, 8), ("f32", f32, 4)):
             b = BYTES_PER_CELL[("step", esz)]
