@@ -505,6 +505,29 @@ __device__ __forceinline__ T combine(T q, T b, T s, double dtx, T idx) {
   }
 }
 
+// ---- CFL wave speed (item 1 of the Heun list) -------------------------------
+//
+// (|u| + c)/dx + (|v| + c)/dy of a cell from its conservative values, and
+// whether the cell is physical (rho > 0, p > 0, finite speed).  One
+// routine for every kernel that reduces it (lf_dt, the corrector epilogue,
+// the single pass), so that they agree bit for bit; the products are
+// written as fmas (the build does not contract).
+template <typename T>
+__device__ __forceinline__ T cfl_speed(T q0, T q1, T q2, T q3, T gm1, T gam, T idx, T idy, bool& ok) {
+  const T ir = rcp(q0);
+  const T uu = q1 * ir, vv = q2 * ir;
+  const T pp = gm1 * fma(T(-0.5), fma(q1, uu, q2 * vv), q3);
+  const T c2 = gam * pp * ir;
+  const T cs = c2 * rsq(c2);
+  const T sp = fma(fabs(uu) + cs, idx, (fabs(vv) + cs) * idy);
+  ok = (q0 > T(0)) && (pp > T(0)) && (sp <= T(3.0e38));
+  return sp;
+}
+// running maximum of the speeds (non-negative, finite where used): a
+// compare and a select, with none of the quieting an IEEE max needs for an
+// operand carried from the previous row
+__device__ __forceinline__ double speed_max(double m, double s) { return s > m ? s : m; }
+
 // ---- wave-level reductions --------------------------------------------------
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {

@@ -283,16 +283,11 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     }
     if constexpr (MODE == kCorrector) {
       if (a.reduce) {
-        // CFL wave speed of the new state, (|u|+c)/dx + (|v|+c)/dy
-        const T ir = rcp(u0);
-        const T uu = u1 * ir, vv = u2 * ir;
-        const T pp = gm1 * (u3 - T(0.5) * (u1 * uu + u2 * vv));
-        const T c2 = gam * pp * ir;
-        const T cs = c2 * rsq(c2);
-        const T sp = (fabs(uu) + cs) * a.idx + (fabs(vv) + cs) * a.idy;
-        const bool ok = (u0 > T(0)) && (pp > T(0)) && (sp <= T(3.0e38));
+        // CFL wave speed of the new state
+        bool ok;
+        const T sp = cfl_speed(u0, u1, u2, u3, gm1, gam, a.idx, a.idy, ok);
         if (out_lane) {
-          if (ok) smax = fmax(smax, double(sp));
+          if (ok) smax = speed_max(smax, double(sp));
           else bad = true;
         }
       }
@@ -328,14 +323,9 @@ __global__ __launch_bounds__(256) void wavespeed_kernel(const T* __restrict__ U,
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride) {
     T q0 = U[q], q1 = U[plane + q], q2 = U[2 * plane + q], q3 = U[3 * plane + q];
-    const T ir = rcp(q0);
-    const T uu = q1 * ir, vv = q2 * ir;
-    const T pp = gm1 * (q3 - T(0.5) * (q1 * uu + q2 * vv));
-    const T c2 = gamma * pp * ir;
-    const T cs = c2 * rsq(c2);
-    const T s = (fabs(uu) + cs) * idx + (fabs(vv) + cs) * idy;
-    const bool ok = (q0 > T(0)) && (pp > T(0)) && (s <= T(3.0e38));
-    if (ok) smax = fmax(smax, double(s));
+    bool ok;
+    const T s = cfl_speed(q0, q1, q2, q3, gm1, gamma, idx, idy, ok);
+    if (ok) smax = speed_max(smax, double(s));
     else bad = true;
   }
   unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(smax));

@@ -388,16 +388,11 @@ void fused_step_kernel(FusedArgs<T> a) {
       C1[f] = fresh ? S1[f] : C1[f];
     }
     if (a.reduce) {
-      // CFL wave speed of the new state, (|u|+c)/dx + (|v|+c)/dy
-      const T ir = rcp(u[0]);
-      const T uu = u[1] * ir, vv = u[2] * ir;
-      const T pp = gm1 * (u[3] - T(0.5) * (u[1] * uu + u[2] * vv));
-      const T c2 = gam * pp * ir;
-      const T cs = c2 * rsq(c2);
-      const T sp = (fabs(uu) + cs) * a.idx + (fabs(vv) + cs) * a.idy;
-      const bool ok = (u[0] > T(0)) && (pp > T(0)) && (sp <= T(3.0e38));
+      // CFL wave speed of the new state
+      bool ok;
+      const T sp = cfl_speed(u[0], u[1], u[2], u[3], gm1, gam, a.idx, a.idy, ok);
       if (out_lane) {
-        if (ok) smax = fmax(smax, double(sp));
+        if (ok) smax = speed_max(smax, double(sp));
         else bad = true;
       }
     }
