@@ -403,13 +403,15 @@ void adjoint_kernel(AdjArgs<T> a) {
       }
       tot = p4_add(tot, tx);
       // primitive -> conservative: v = (dw/dU)^T wbar
+      // (products written as fmas: the build does not contract)
       const T ir = rcp(Wm2.r);
       const T u = Wm2.u, v = Wm2.v;
+      const T gp = gm1 * tot.p;
       T vv[4];
-      vv[0] = tot.r - (u * tot.u + v * tot.v) * ir + gm1 * T(0.5) * (u * u + v * v) * tot.p;
-      vv[1] = tot.u * ir - gm1 * u * tot.p;
-      vv[2] = tot.v * ir - gm1 * v * tot.p;
-      vv[3] = gm1 * tot.p;
+      vv[0] = fma(T(0.5) * gp, fma(u, u, v * v), fma(-fma(u, tot.u, v * tot.v), ir, tot.r));
+      vv[1] = fma(-gp, u, tot.u * ir);
+      vv[2] = fma(-gp, v, tot.v * ir);
+      vv[3] = gp;
       const T gg[4] = {Gm2.r, Gm2.u, Gm2.v, Gm2.p};
       if constexpr (MODE == kAdjPred) lam_wait();
 #pragma unroll
@@ -417,10 +419,10 @@ void adjoint_kernel(AdjArgs<T> a) {
         if constexpr (MODE == kVjp) {
           res[f] = vv[f];
         } else if constexpr (MODE == kAdjCorr) {
-          res[f] = T(0.5 * (double(gg[f]) - a.dt * double(vv[f])));  // mu = (lam - dt v)/2
+          res[f] = T(0.5 * fma(-a.dt, double(vv[f]), double(gg[f])));  // mu = (lam - dt v)/2
         } else {
           const T lam = lam_at(f);  // lam/2 + mu - dt v
-          res[f] = T(0.5 * double(lam) + double(gg[f]) - a.dt * double(vv[f]));
+          res[f] = T(fma(0.5, double(lam), fma(-a.dt, double(vv[f]), double(gg[f]))));
         }
       }
     }
