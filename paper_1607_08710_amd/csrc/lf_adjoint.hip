@@ -133,11 +133,13 @@ __device__ __forceinline__ SlopeD<T> slope_d(const P4<T>& dm, const P4<T>& dp, T
 // One face: left cell state w1 with slope data S1 (cell k-1), right cell
 // w2 with S2 (cell k); fb the flux cotangent in the face frame.  Returns
 // the four slot contributions in (rho, u, v, p) order.  YF selects the
-// y-face frame (normal velocity v).
+// y-face frame (normal velocity v); then slot 0 comes back with acc0 (the
+// running sum of its row) added.
 template <typename T, bool YF>
 __device__ __forceinline__ void face_slots(const P4<T>& w1, const SlopeD<T>& S1, const P4<T>& w2,
                                            const SlopeD<T>& S2, const Flux<T>& fb, T gamma, T inv_gm1,
-                                           P4<T>& s0, P4<T>& s1, P4<T>& s2, P4<T>& s3) {
+                                           P4<T>& s0, P4<T>& s1, P4<T>& s2, P4<T>& s3,
+                                           const P4<T>& acc0 = P4<T>{}) {
   const T h = T(0.5);
   const P4<T> L = {fma(h, S1.s.r, w1.r), fma(h, S1.s.u, w1.u), fma(h, S1.s.v, w1.v), fma(h, S1.s.p, w1.p)};
   const P4<T> R = {fma(-h, S2.s.r, w2.r), fma(-h, S2.s.u, w2.u), fma(-h, S2.s.v, w2.v), fma(-h, S2.s.p, w2.p)};
@@ -160,16 +162,19 @@ __device__ __forceinline__ void face_slots(const P4<T>& w1, const SlopeD<T>& S1,
   }
   // w^L = w1 + phi(w1 - w0, w2 - w1)/2,  w^R = w2 - phi(w2 - w1, w3 - w2)/2;
   // a1, b1 (a2, b2): half partials of the left (right) cell's slope
-  auto one = [&](T l, T r, T a1, T b1, T a2, T b2, T& o0, T& o1, T& o2, T& o3) {
-    o0 = -a1 * l;
+  // (y-faces: slot 0 is added straight into the accumulator acc0 of its
+  // row, one fma instead of a product and an add)
+  auto one = [&](T l, T r, T a1, T b1, T a2, T b2, T c0, T& o0, T& o1, T& o2, T& o3) {
+    if constexpr (YF) o0 = fma(-a1, l, c0);
+    else o0 = -a1 * l;
     o1 = fma(a1 - b1, l, fma(a2, r, l));
     o2 = fma(b1, l, fma(b2 - a2, r, r));
     o3 = -b2 * r;
   };
-  one(lb.r, rb.r, S1.hda.r, S1.hdb.r, S2.hda.r, S2.hdb.r, s0.r, s1.r, s2.r, s3.r);
-  one(lb.u, rb.u, S1.hda.u, S1.hdb.u, S2.hda.u, S2.hdb.u, s0.u, s1.u, s2.u, s3.u);
-  one(lb.v, rb.v, S1.hda.v, S1.hdb.v, S2.hda.v, S2.hdb.v, s0.v, s1.v, s2.v, s3.v);
-  one(lb.p, rb.p, S1.hda.p, S1.hdb.p, S2.hda.p, S2.hdb.p, s0.p, s1.p, s2.p, s3.p);
+  one(lb.r, rb.r, S1.hda.r, S1.hdb.r, S2.hda.r, S2.hdb.r, acc0.r, s0.r, s1.r, s2.r, s3.r);
+  one(lb.u, rb.u, S1.hda.u, S1.hdb.u, S2.hda.u, S2.hdb.u, acc0.u, s0.u, s1.u, s2.u, s3.u);
+  one(lb.v, rb.v, S1.hda.v, S1.hdb.v, S2.hda.v, S2.hdb.v, acc0.v, s0.v, s1.v, s2.v, s3.v);
+  one(lb.p, rb.p, S1.hda.p, S1.hdb.p, S2.hda.p, S2.hdb.p, acc0.p, s0.p, s1.p, s2.p, s3.p);
 }
 
 template <typename T>
@@ -351,8 +356,8 @@ void adjoint_kernel(AdjArgs<T> a) {
       const Flux<T> fb = {(Gm1.r - Gk.r) * a.idy, (Gm1.v - Gk.v) * a.idy, (Gm1.u - Gk.u) * a.idy,
                           (Gm1.p - Gk.p) * a.idy};
       P4<T> s0, s1, s2, s3;
-      face_slots<T, true>(Wm1, Sk1, W0, Sk, fb, gam, igm1, s0, s1, s2, s3);
-      Am2 = p4_add(Am2, s0);
+      face_slots<T, true>(Wm1, Sk1, W0, Sk, fb, gam, igm1, s0, s1, s2, s3, Am2);
+      Am2 = s0;  // the accumulator of row k-2 with slot 0 added
       Am1 = p4_add(Am1, s1);
       A0 = p4_add(A0, s2);
       A1 = s3;

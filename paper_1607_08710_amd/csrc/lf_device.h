@@ -408,29 +408,35 @@ __device__ __forceinline__ void face_flux_vjp(const FaceState<T>& L, const FaceS
   const T habr = T(0.5) * ab * irs;
   const T dar = -habr * a;
   const T dap = habr * (gamma * ia);
-  // the sound-speed and upwind terms each go to one side: the left
-  // side's share is selected and the right side takes the rest, x - share,
-  // which is exactly x or 0
-  T darL, dapL, rbL, unbL, utbL, pbL;
+  // the sound-speed and upwind terms each go to one side
   if constexpr (sizeof(T) == 8) {
-    // weights 1 or 0 (one select each, the low word being zero) instead of
-    // a select per double: x w is x or a zero
+    // 0/1 weights of the two sides (one select each, the low word being
+    // zero, where a select of a double takes two), folded into fmas
     const T wa = aleft ? T(1) : T(0), wl = left ? T(1) : T(0);
-    darL = dar * wa, dapL = dap * wa;
-    rbL = rb * wl, unbL = unb * wl, utbL = utb * wl, pbL = pb * wl;
+    const T va = aleft ? T(0) : T(1), vl = left ? T(0) : T(1);
+    Lb.r = fma(dar, wa, fma(rb, wl, rlb));
+    Lb.un = fma(unb, wl, unlb);
+    Lb.ut = utb * wl;
+    Lb.p = fma(dap, wa, fma(pb, wl, plb));
+    Rb.r = fma(dar, va, fma(rb, vl, rrb));
+    Rb.un = fma(unb, vl, unrb);
+    Rb.ut = utb * vl;
+    Rb.p = fma(dap, va, fma(pb, vl, prb));
   } else {
-    darL = aleft ? dar : T(0), dapL = aleft ? dap : T(0);
-    rbL = left ? rb : T(0), unbL = left ? unb : T(0);
-    utbL = left ? utb : T(0), pbL = left ? pb : T(0);
+    // the left side's share is selected and the right side takes the
+    // rest, x - share, which is exactly x or 0
+    const T darL = aleft ? dar : T(0), dapL = aleft ? dap : T(0);
+    const T rbL = left ? rb : T(0), unbL = left ? unb : T(0);
+    const T utbL = left ? utb : T(0), pbL = left ? pb : T(0);
+    Lb.r = rlb + darL + rbL;
+    Lb.un = unlb + unbL;
+    Lb.ut = utbL;
+    Lb.p = plb + dapL + pbL;
+    Rb.r = rrb + (dar - darL) + (rb - rbL);
+    Rb.un = unrb + (unb - unbL);
+    Rb.ut = utb - utbL;
+    Rb.p = prb + (dap - dapL) + (pb - pbL);
   }
-  Lb.r = rlb + darL + rbL;
-  Lb.un = unlb + unbL;
-  Lb.ut = utbL;
-  Lb.p = plb + dapL + pbL;
-  Rb.r = rrb + (dar - darL) + (rb - rbL);
-  Rb.un = unrb + (unb - unbL);
-  Rb.ut = utb - utbL;
-  Rb.p = prb + (dap - dapL) + (pb - pbL);
 }
 
 // ---- pieces of a stage row shared by the stage kernels ----------------------
