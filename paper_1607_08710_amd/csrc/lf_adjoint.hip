@@ -408,12 +408,14 @@ void adjoint_kernel(AdjArgs<T> a) {
       }
       tot = p4_add(tot, tx);
       // primitive -> conservative: v = (dw/dU)^T wbar
-      // (products written as fmas: the build does not contract)
+      // (products written as fmas, the build does not contract, except in
+      // the sums over the two directions, which keep the x <-> y mirror
+      // symmetry exact)
       const T ir = rcp(Wm2.r);
       const T u = Wm2.u, v = Wm2.v;
       const T gp = gm1 * tot.p;
       T vv[4];
-      vv[0] = fma(T(0.5) * gp, fma(u, u, v * v), fma(-fma(u, tot.u, v * tot.v), ir, tot.r));
+      vv[0] = fma(T(0.5) * gp, u * u + v * v, fma(-(u * tot.u + v * tot.v), ir, tot.r));
       vv[1] = fma(-gp, u, tot.u * ir);
       vv[2] = fma(-gp, v, tot.v * ir);
       vv[3] = gp;

@@ -167,9 +167,11 @@ __device__ __forceinline__ Prim<T> to_prim(T q0, T q1, T q2, T q3, T gm1) {
   w.r = q0;
   w.u = q1 * ir;
   w.v = q2 * ir;
-  // p = (gamma-1) (rho E - (m_x u + m_y v)/2)
-  T ke = T(0.5) * (q1 * w.u + q2 * w.v);
-  w.p = gm1 * (q3 - ke);
+  // p = (gamma-1) (rho E - (m_x u + m_y v)/2): the sum of the two rounded
+  // products keeps the x <-> y mirror symmetry exact (an fma over one of
+  // them would not); the halving is exact, so one fma takes it and the
+  // difference with the same rounding as a product and a subtraction
+  w.p = gm1 * fma(T(-0.5), q1 * w.u + q2 * w.v, q3);
   return w;
 }
 
@@ -269,8 +271,7 @@ __device__ __forceinline__ FaceState<T> face_prim(const FaceState<T>& f, T gm1) 
   } else {
     const T ir = rcp(f.r);
     const T un = f.un * ir, ut = f.ut * ir;
-    const T ke = T(0.5) * (f.un * un + f.ut * ut);
-    return {f.r, un, ut, gm1 * (f.p - ke)};
+    return {f.r, un, ut, gm1 * fma(T(-0.5), f.un * un + f.ut * ut, f.p)};
   }
 }
 
@@ -516,16 +517,15 @@ __device__ __forceinline__ T combine(T q, T b, T s, double dtx, T idx) {
 // (|u| + c)/dx + (|v| + c)/dy of a cell from its conservative values, and
 // whether the cell is physical (rho > 0, p > 0, finite speed).  One
 // routine for every kernel that reduces it (lf_dt, the corrector epilogue,
-// the single pass), so that they agree bit for bit; the products are
-// written as fmas (the build does not contract).
+// the single pass), so that they agree bit for bit; symmetric in x and y.
 template <typename T>
 __device__ __forceinline__ T cfl_speed(T q0, T q1, T q2, T q3, T gm1, T gam, T idx, T idy, bool& ok) {
   const T ir = rcp(q0);
   const T uu = q1 * ir, vv = q2 * ir;
-  const T pp = gm1 * fma(T(-0.5), fma(q1, uu, q2 * vv), q3);
+  const T pp = gm1 * fma(T(-0.5), q1 * uu + q2 * vv, q3);  // as to_prim
   const T c2 = gam * pp * ir;
   const T cs = c2 * rsq(c2);
-  const T sp = fma(fabs(uu) + cs, idx, (fabs(vv) + cs) * idy);
+  const T sp = (fabs(uu) + cs) * idx + (fabs(vv) + cs) * idy;
   ok = (q0 > T(0)) && (pp > T(0)) && (sp <= T(3.0e38));
   return sp;
 }
