@@ -184,8 +184,10 @@ __device__ __forceinline__ void window_row(Win<T, NS>& W, const RowV<T, NS>& rn,
 // cell and step without fractions), so its LDS footprint is kept small for
 // occupancy: U^n of the rows still to be combined waits in a per-wave LDS
 // ring, U* of the two rows waiting for the corrector's combination stays in
-// registers, and one LDS row of U* serves the reads across lanes.  Results
-// are stored straight from the lanes (no staging, no block barrier).
+// registers, and one LDS row of U* serves the reads across lanes where they
+// are needed (transmissive x) and in FP32 (where the round trip through LDS
+// saves the registers that a fifth wave per SIMD needs).  Results are
+// stored straight from the lanes (no staging, no block barrier).
 template <typename T, int BCX, int BCY, int NS, bool CONS>
 __global__ __launch_bounds__(kWave * kFusedWaves) __attribute__((amdgpu_waves_per_eu(fused_min_waves<T, BCX, BCY, NS, CONS>())))
 void fused_step_kernel(FusedArgs<T> a) {
@@ -194,6 +196,7 @@ void fused_step_kernel(FusedArgs<T> a) {
   constexpr int WPB = kFusedWaves;
   constexpr bool XT = BCX == kBcTransmissive;
   constexpr bool YT = BCY == kBcTransmissive;
+  constexpr bool SROW = XT || sizeof(T) == 4;  // U* rows pass through LDS
   if (a.dt_dev && a.ctl->done) return;
   const int lb = xcd_block(blockIdx.x, a.blocks_pad);
   if (lb >= a.blocks) return;  // whole block
@@ -252,9 +255,9 @@ void fused_step_kernel(FusedArgs<T> a) {
   // U^n ring (rows o .. o+4 are alive while row o is finished) and the
   // U* row exchanged across lanes.
   __shared__ T nring[WPB][5][NF][kWave];
-  __shared__ T srow[WPB][NF][kWave];
+  __shared__ T srow[WPB][NF][SROW ? kWave : 1];
   T(*my_n)[NF][kWave] = nring[w];
-  T(*my_s)[kWave] = srow[w];
+  T(*my_s)[SROW ? kWave : 1] = srow[w];
   auto nslot = [](int r) { return (r % 5 + 5) % 5; };
   auto put_n = [&](int r, const T (&q)[NF]) {
     const int sl = nslot(r);
@@ -297,7 +300,7 @@ void fused_step_kernel(FusedArgs<T> a) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) S0[f] = S1[f] = T(0);
   // U* row pr = U^n - dt R(U^n); it goes to S1 (S1 moves to S0) and to the
-  // LDS row read across lanes
+  // LDS row read across lanes (when there is one)
   auto produce = [&]() {
     const RowV<T, NS> rn = row_vars<CONS, NS>(QA, gm1);  // U^n row pr+2
     put_n(pr + 2, QA);
@@ -314,7 +317,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     for (int f = 0; f < NF; ++f) {
       S0[f] = S1[f];
       S1[f] = combine<kPredictor>(my_n[sn][f][lane], T(0), bal[f], dtx, idx);
-      my_s[f][lane] = S1[f];
+      if constexpr (SROW) my_s[f][lane] = S1[f];
     }
     // U* of the strip's own rows, when asked for (halo rows belong to the
     // neighbouring strips)
@@ -329,11 +332,15 @@ void fused_step_kernel(FusedArgs<T> a) {
   // reconstruction variables of the newest U* row produced, at this lane's
   // column (ghost lanes: the edge column)
   auto star_row = [&]() {
-    T q[NF];
-    __builtin_amdgcn_wave_barrier();
+    if constexpr (SROW) {
+      T q[NF];
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int f = 0; f < NF; ++f) q[f] = my_s[f][src];
-    return row_vars<CONS, NS>(q, gm1);
+      for (int f = 0; f < NF; ++f) q[f] = my_s[f][src];
+      return row_vars<CONS, NS>(q, gm1);
+    } else {
+      return row_vars<CONS, NS>(S1, gm1);  // src == lane
+    }
   };
 
   // ---- corrector: window of row y0 from U* rows y0-2 .. y0+1 ----
