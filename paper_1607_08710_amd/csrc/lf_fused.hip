@@ -61,16 +61,34 @@ struct FusedArgs {
 template <typename T, int NS>
 constexpr bool regs_to_spare() { return !(sizeof(T) == 8 && NS >= 2); }
 
+// FP64 without mass fractions, periodic in x, periodic or ghost-row in y,
+// with the primitive reconstruction: with one row of U^n in flight ahead
+// of the predictor instead of two it needs 167 VGPRs, which leaves three
+// waves per SIMD instead of two (1.5% faster at 16384^2).  The variants
+// that stay at two waves keep two rows in flight (one row is up to 3%
+// slower there).
+template <typename T, int BCX, int BCY, int NS, bool CONS>
+constexpr bool fp64_three_waves() {
+  return sizeof(T) == 8 && NS == 0 && !CONS && BCX == kBcPeriodic && BCY != kBcTransmissive;
+}
+
 // Waves per SIMD the compiler must leave room for.  FP32 without mass
 // fractions, periodic in x and periodic or ghost-row in y, with the
 // primitive reconstruction, fits five (96 VGPRs without a spill), which
 // runs 2% faster than the four its unconstrained 97-register allocation
 // allows; the other variants would spill at 96 and take what their
-// registers allow.
+// registers allow.  FP64: three where fp64_three_waves() holds.
 template <typename T, int BCX, int BCY, int NS, bool CONS>
 constexpr int fused_min_waves() {
-  return sizeof(T) == 4 && NS == 0 && !CONS && BCX == kBcPeriodic && BCY != kBcTransmissive ? 5 : 1;
+  if constexpr (sizeof(T) == 4)
+    return NS == 0 && !CONS && BCX == kBcPeriodic && BCY != kBcTransmissive ? 5 : 1;
+  else
+    return fp64_three_waves<T, BCX, BCY, NS, CONS>() ? 3 : 1;
 }
+
+// Rows of U^n in flight ahead of the predictor: one or two.
+template <typename T, int BCX, int BCY, int NS, bool CONS>
+constexpr int fused_ahead() { return fp64_three_waves<T, BCX, BCY, NS, CONS>() ? 1 : 2; }
 
 // Reconstruction variables of one row: the Euler part (primitive, or
 // conservative under CONS) and the mass fractions y_k = (rho y_k) / rho.
@@ -275,8 +293,8 @@ void fused_step_kernel(FusedArgs<T> a) {
   const int phi = YT ? min(y1 + 1, ny - 1) : y1 + 1;
   const int nlast = phi + 2;  // last U^n row the predictor reads
 
-  // ---- predictor: window of row plo, U^n rows plo+2 and plo+3 in flight ----
-  T QA[NF], QB[NF];
+  // ---- predictor: window of row plo, U^n row plo+2 (and plo+3) in flight ----
+  T QA[NF], QB[NF];  // U^n rows pr+2 and (two rows in flight) pr+3
 #pragma unroll
   for (int f = 0; f < NF; ++f) QB[f] = T(0);
   Win<T, NS> PW;
@@ -287,7 +305,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     load_row(plo, q0);
     load_row(plo + 1, q1);
     load_row(plo + 2, QA);
-    load_row(min(plo + 3, nlast), QB);
+    if constexpr (fused_ahead<T, BCX, BCY, NS, CONS>() == 2) load_row(min(plo + 3, nlast), QB);
     put_n(plo, q0);
     put_n(plo + 1, q1);
     PW = prime_window<CONS, NS>(row_vars<CONS, NS>(qa, gm1), row_vars<CONS, NS>(qb, gm1),
@@ -304,12 +322,16 @@ void fused_step_kernel(FusedArgs<T> a) {
   auto produce = [&]() {
     const RowV<T, NS> rn = row_vars<CONS, NS>(QA, gm1);  // U^n row pr+2
     put_n(pr + 2, QA);
+    // the next row, unconditional (past the last row it re-reads that row,
+    // unused), so that the compiler can count the loads in flight and wait
+    // only for the row it needs, not for the one loaded a row later
+    if constexpr (fused_ahead<T, BCX, BCY, NS, CONS>() == 2) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) QA[f] = QB[f];
-    // unconditional (past the last row it re-reads that row, unused), so
-    // that the compiler can count the loads in flight and wait only for the
-    // row it needs, not for the one loaded a row later
-    load_row(min(pr + 4, nlast), QB);
+      for (int f = 0; f < NF; ++f) QA[f] = QB[f];
+      load_row(min(pr + 4, nlast), QB);
+    } else {
+      load_row(min(pr + 3, nlast), QA);
+    }
     T bal[NF];  // flux balances
     window_row<CONS, NS>(PW, rn, beta, h, gam, gm1, igm1, kxy, bal);
     const int sn = nslot(pr);
