@@ -66,7 +66,7 @@ def test_kernel_registers(kernel_asm):
     registers).  (SGPR spills go
     to VGPR lanes, not to memory, and are not counted.)  The FP32
     single-pass step of the benchmark fits five waves per SIMD (at most 96
-    VGPRs), the FP64 one three (at most 168)."""
+    VGPRs), the FP64 one three (at most 168), also as a strip step."""
     regs = {}
     for src in ("lf_forward.hip", "lf_fused.hip", "lf_adjoint.hip"):
         regs.update(_registers(kernel_asm[src]))
@@ -75,3 +75,4 @@ def test_kernel_registers(kernel_asm):
     assert spills == {"_ZN2lf17fused_step_kernelIdLi1ELi2ELi4ELb0EEEvNS_9FusedArgsIT_EE": 2}, spills
     assert regs["_ZN2lf17fused_step_kernelIfLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"][0] <= 96
     assert regs["_ZN2lf17fused_step_kernelIdLi0ELi0ELi0ELb0EEEvNS_9FusedArgsIT_EE"][0] <= 168
+    assert regs["_ZN2lf17fused_step_kernelIdLi0ELi2ELi0ELb0EEEvNS_9FusedArgsIT_EE"][0] <= 168  # strip step
