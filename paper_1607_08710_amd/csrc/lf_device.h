@@ -531,8 +531,11 @@ __device__ __forceinline__ T cfl_speed(T q0, T q1, T q2, T q3, T gm1, T gam, T i
 }
 // running maximum of the speeds (non-negative, finite where used): a
 // compare and a select, with none of the quieting an IEEE max needs for an
-// operand carried from the previous row
-__device__ __forceinline__ double speed_max(double m, double s) { return s > m ? s : m; }
+// operand carried from the previous row.  Kept in the state's precision (a
+// maximum is exact in any precision) and widened once, for the reduction
+// across lanes in FP64.
+template <typename T>
+__device__ __forceinline__ T speed_max(T m, T s) { return s > m ? s : m; }
 
 // ---- wave-level reductions --------------------------------------------------
 

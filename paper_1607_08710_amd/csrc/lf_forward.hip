@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
     }
   }
 
-  double smax = 0.0;
+  T smax = T(0);
   bool bad = false;
 
   // Row o: qc holds row o+2 (arrived) and then receives row o+4; bc holds
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
         bool ok;
         const T sp = cfl_speed(u0, u1, u2, u3, gm1, gam, a.idx, a.idy, ok);
         if (out_lane) {
-          if (ok) smax = speed_max(smax, double(sp));
+          if (ok) smax = speed_max(smax, sp);
           else bad = true;
         }
       }
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
 
   if constexpr (MODE == kCorrector) {
     if (a.reduce) {
-      unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(smax));
+      unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(double(smax)));
       unsigned long long anybad = __ballot(bad);
       if (lane == 0) {
         if (m) atomicMax(&a.ctl->smax, m);
@@ -320,17 +320,17 @@ __global__ __launch_bounds__(kWave * waves_per_block<T>()) void stage_kernel(Sta
 template <typename T>
 __global__ __launch_bounds__(256) void wavespeed_kernel(const T* __restrict__ U, long long plane,
                                                         T gamma, T gm1, T idx, T idy, Ctl* ctl) {
-  double smax = 0.0;
+  T smax = T(0);
   bool bad = false;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane; q += stride) {
     T q0 = U[q], q1 = U[plane + q], q2 = U[2 * plane + q], q3 = U[3 * plane + q];
     bool ok;
     const T s = cfl_speed(q0, q1, q2, q3, gm1, gamma, idx, idy, ok);
-    if (ok) smax = speed_max(smax, double(s));
+    if (ok) smax = speed_max(smax, s);
     else bad = true;
   }
-  unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(smax));
+  unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(double(smax)));
   unsigned long long anybad = __ballot(bad);
   if ((threadIdx.x & (kWave - 1)) == 0) {
     if (m) atomicMax(&ctl->smax, m);

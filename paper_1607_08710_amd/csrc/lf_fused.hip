@@ -390,7 +390,7 @@ void fused_step_kernel(FusedArgs<T> a) {
     }
   }
 
-  double smax = 0.0;
+  T smax = T(0);
   bool bad = false;
 
   // One corrector row (and the predictor row two ahead of it).
@@ -421,7 +421,7 @@ void fused_step_kernel(FusedArgs<T> a) {
       bool ok;
       const T sp = cfl_speed(u[0], u[1], u[2], u[3], gm1, gam, a.idx, a.idy, ok);
       if (out_lane) {
-        if (ok) smax = speed_max(smax, double(sp));
+        if (ok) smax = speed_max(smax, sp);
         else bad = true;
       }
     }
@@ -446,7 +446,7 @@ void fused_step_kernel(FusedArgs<T> a) {
   for (; o < y1; ++o) row(o);
 
   if (a.reduce) {
-    unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(smax));
+    unsigned long long m = wave_max_u64((unsigned long long)__double_as_longlong(double(smax)));
     unsigned long long anybad = __ballot(bad);
     if (lane == 0) {
       if (m) atomicMax(&a.ctl->smax, m);
