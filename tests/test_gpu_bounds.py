@@ -123,3 +123,24 @@ def test_variant_step_outputs_in_bounds(variant, bc):
     o = Guarded(S)
     S.step(U, o.out, dt)
     o.check(f"lf_step {variant}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bcx", [0, 1])
+@pytest.mark.parametrize("shape", [(61, 1), (61, 3), (130, 37), (9, 5)])
+def test_strip_step_outputs_in_bounds(shape, bcx, dtype):
+    """lf_step_halo (ghost rows given) on strips shorter and taller than
+    the ghost rows: every output element written, nothing beyond."""
+    import torch
+    nx, ny = shape
+    cfg = _cfg(nx, ny, bcx, 0)
+    S = solver_for(cfg, dtype)
+    U, dt, _ = _inputs(S, cfg, 3 + ny)
+    gl = workloads.random_state(nx, 4, seed=100 + ny)
+    gh = workloads.random_state(nx, 4, seed=200 + ny)
+    glo, ghi = to_dev(gl, dtype).contiguous(), to_dev(gh, dtype).contiguous()
+    assert tuple(glo.shape) == (4, 4, nx) and glo.dtype == S.torch_dtype
+    o = Guarded(S)
+    S.step_halo(U, glo, ghi, o.out, dt)
+    torch.cuda.synchronize()
+    o.check(f"lf_step_halo {shape}")
