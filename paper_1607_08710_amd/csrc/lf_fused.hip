@@ -34,7 +34,8 @@ constexpr int kFHalo = 4;
 constexpr int kFTileW = kWave - 2 * kFHalo;  // 56 output columns per wave
 // Waves per block, both precisions (the waves are independent; a block
 // only numbers adjacent tiles).  Measured at 16384^2: FP32 runs 2.5%
-// faster than with 8, FP64 0.7% faster than with 2.
+// faster than with 8; FP64 runs as fast as with 2 and 12-28% faster than
+// with 6.
 constexpr int kFusedWaves = 4;
 
 template <typename T>
@@ -460,10 +461,10 @@ void fused_step_kernel(FusedArgs<T> a) {
 // 16384^2 in FP64; in FP32 128 rows are within 1% there and 5% slower at
 // 8192^2).  FP64 halves it to 64 rows while the launch has fewer than
 // 16384 waves (at 8192^2 64 rows are 2.5-3% faster than 128).  Then it is
-// halved (down to 8) until there are about two waves per wave slot of the
-// chip: 4096 waves in FP64 (2 waves per SIMD), 8192 in FP32, the best
-// measured at 4096^2.  LF_FUSED_ROWS (4..4096) overrides it.  The launch
-// shape never changes the result.
+// halved (down to 8) until the launch has 4096 waves in FP64 or 8192 in
+// FP32, the best measured at 4096^2 (for FP64 at two and at three waves
+// per SIMD).  LF_FUSED_ROWS (4..4096) overrides it.  The launch shape never
+// changes the result.
 static int fused_rows(int nx, int ny, int esize) {
   const long long tiles_x = (nx + kFTileW - 1) / kFTileW;
   auto waves = [&](int r) { return tiles_x * ((ny + r - 1) / r); };
